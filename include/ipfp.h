@@ -1,0 +1,215 @@
+/*
+ * ipfp.h -- C ABI of the MI355X (gfx950) IPFP library for Choo-Siow
+ * transferable-utility matching markets.
+ *
+ * The library solves the welfare program of the paper's Sec. 3.1 (eq. 2-3)
+ * by the IPFP sweep of Sec. 3.2 (eq. 6-7): with u_x = sqrt(mu_x0) and
+ * v_y = sqrt(mu_0y), every sweep sets
+ *     u_x <- n_x / (s_x + sqrt(s_x^2 + n_x)),  s_x = (1/2) sum_y K_xy v_y,
+ *     v_y <- m_y / (s_y + sqrt(s_y^2 + m_y)),  s_y = (1/2) sum_x K_xy u_x,
+ * with K = exp(Phi / (2 sigma)) and v starting at 1. The root is the
+ * rationalised form of eq. 6's sqrt(n + s^2) - s (the same number, without
+ * the cancellation). The surplus is either given as a dense matrix (batch
+ * IPFP, eq. 7) or as the low-rank product Phi = U V^T + Q P^T of eq. 8, in
+ * which case the fused path never stores K (mini-batch IPFP, eq. 9-10).
+ * Matching masses follow eq. 4: mu_xy = K_xy a_x b_y, mu_x0 = a_x^2,
+ * mu_0y = b_y^2, with a = u and b = v.
+ *
+ * Names: n (length N) are the row (candidate) margins and m (length M) the
+ * column (employer) margins, as in eq. 2 (the appendix's algorithms swap the
+ * two letters). sigma is the paper's entropy scale beta.
+ *
+ * Convergence: after sweep i, when i is a multiple of check_every or equals
+ * max_sweeps, the residual r = max_x |a_x^2 + a_x (K b)_x - n_x| / n_x of the
+ * current (a, b) is recorded (eq. 5's row equation; its column equation holds
+ * to rounding right after each v update). The solve stops when r < tol and
+ * returns that sweep's (a, b); tol = 0 runs exactly max_sweeps sweeps.
+ *
+ * Conventions for every entry point:
+ *  - Return value: IPFP_OK (0), a positive status (results valid), or a
+ *    negative error code; nothing is thrown across the ABI.
+ *  - Pointers named "device" are HIP device pointers on the context's device;
+ *    "host" pointers are ordinary host memory. The caller owns every input
+ *    and output buffer; the library owns only its scratch memory, which is
+ *    charged against the context's HBM budget.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
+ *    device work is ordered on it. Calls that return results to the host
+ *    synchronise that stream before returning.
+ *  - Matrices are row-major with a leading dimension (row stride) given in
+ *    elements, >= the row length.
+ *  - Inputs are validated before any launch: N, M >= 1; 1 <= d <= 256;
+ *    sigma > 0 and finite; n and m must be > 0 and finite (checked on the
+ *    device; a violation gives IPFP_EINVAL). Non-finite factor or surplus
+ *    values give IPFP_ENONFINITE.
+ */
+#ifndef IPFP_H
+#define IPFP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IPFP_ABI_VERSION 1
+
+typedef enum {
+  IPFP_F64 = 0,      /* IEEE binary64 */
+  IPFP_F32 = 1,      /* IEEE binary32 */
+  IPFP_BF16 = 2,     /* bfloat16 (upper half of binary32) */
+  IPFP_FP8E4M3 = 3   /* OCP FP8 e4m3fn with a power-of-two scale per row */
+} ipfp_dtype;
+
+typedef enum {
+  IPFP_PATH_FUSED = 0, /* factors -> on-the-fly MFMA tiles, K never stored */
+  IPFP_PATH_PLAIN = 1  /* K = exp(Phi/2sigma) materialised, two matvecs/sweep */
+} ipfp_path;
+
+enum {
+  IPFP_OK = 0,
+  IPFP_NOT_CONVERGED = 1,   /* tol > 0 not reached in max_sweeps; a, b valid */
+  IPFP_EINVAL = -1,         /* invalid argument */
+  IPFP_EBUDGET = -2,        /* scratch would exceed the context's HBM budget */
+  IPFP_EHIP = -3,           /* a HIP runtime call failed */
+  IPFP_ENONFINITE = -4,     /* non-finite input or non-finite intermediate */
+  IPFP_ECANCELLED = -5,     /* serving request cancelled */
+  IPFP_EBUSY = -6,          /* serving request still queued or running */
+  IPFP_ENOTFOUND = -7       /* unknown serving ticket */
+};
+
+typedef struct ipfp_ctx ipfp_ctx;       /* one per device; internally locked */
+typedef struct ipfp_handle ipfp_handle; /* a market held resident on device */
+
+/* A market given by its factors (eq. 8): Phi = U V^T + Q P^T.
+ * U, Q: N x d device matrices with row stride ld_x; V, P: M x d with ld_y.
+ * All four have dtype `in_dtype` (F64, F32 or BF16). n (N) and m (M) are
+ * device FP64 margins. */
+typedef struct {
+  int64_t N, M, d;
+  ipfp_dtype in_dtype;
+  const void *U, *Q, *V, *P;
+  int64_t ld_x, ld_y;
+  const double *n, *m;
+  double sigma;
+} ipfp_market;
+
+typedef struct {
+  ipfp_path path;        /* FUSED (factors) or PLAIN (materialised K)         */
+  ipfp_dtype compute;    /* FUSED: BF16 or FP8E4M3 or F32 operands for the
+                            surplus tiles (FP32 accumulate, FP32 exp2, FP64
+                            sums and updates). PLAIN: F32 or F64 storage of K
+                            (FP64 sums and updates either way).               */
+  double tol;            /* stop when the row residual < tol; 0 = never       */
+  int32_t max_sweeps;    /* >= 1                                              */
+  int32_t check_every;   /* >= 1: residual cadence (and host sync cadence)    */
+  int32_t splits;        /* reduction splits per half-sweep; 0 = automatic.
+                            Results are bitwise reproducible for fixed
+                            splits; across splits they agree to rounding.     */
+  int32_t tile_rows;     /* FUSED: output rows per workgroup (256 or 512);
+                            0 = automatic                                     */
+  const double *b0;      /* optional device warm start for v (length M);
+                            NULL = ones. The initial u is never read.         */
+  int32_t use_graph;     /* 1 = replay sweeps through a captured hipGraph     */
+  int32_t time_passes;   /* 1 = bracket every reduction-pass launch with HIP
+                            events and report their total in the result       */
+} ipfp_options;
+
+typedef struct {
+  double *a;             /* device, length N: a = u = sqrt(mu_x0) (output)    */
+  double *b;             /* device, length M: b = v = sqrt(mu_0y) (output)    */
+  double *res_hist;      /* host, capacity res_cap: residual at every check   */
+  int32_t res_cap;
+  /* filled by the library */
+  int32_t sweeps;        /* sweeps whose (a, b) are returned                  */
+  int32_t n_res;         /* residuals recorded (may exceed res_cap; only the
+                            first res_cap are stored)                         */
+  double final_res;      /* residual of the returned (a, b)                   */
+  double setup_ms;       /* packing / K materialisation time (host clock)     */
+  double loop_ms;        /* sweep-loop time (HIP events on `stream`)          */
+  double pass_ms;        /* sum of timed reduction-pass launches (ms)         */
+  int32_t pass_launches; /* number of timed reduction-pass launches           */
+  int32_t fixups;        /* rows recomputed by the exact-shift fallback       */
+} ipfp_result;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `hip_device` whose scratch allocations may
+ * total at most `hbm_budget_bytes` (0 = no limit beyond the device's). */
+int ipfp_create(ipfp_ctx **out, int hip_device, size_t hbm_budget_bytes);
+void ipfp_destroy(ipfp_ctx *ctx);
+const char *ipfp_strerror(int code);
+int ipfp_abi_version(void);
+/* The default options: FUSED, BF16, tol 0, 100 sweeps, check every sweep,
+ * automatic splits and tiles, no warm start, no graph, no pass timing. */
+void ipfp_default_options(ipfp_options *opt);
+
+/* Scratch bytes a solve of this market with these options needs. */
+int ipfp_footprint(const ipfp_market *mk, const ipfp_options *opt,
+                   size_t *bytes_out);
+
+/* ---- one-call solves ------------------------------------------------------ */
+
+/* Solve a factor market (eq. 8-10). opt->path selects the fused on-the-fly
+ * kernels (K never stored, mini-batch IPFP of Sec. 3.3) or the plain path,
+ * which materialises K once from the factors (batch IPFP, eq. 7).
+ * Returns IPFP_OK, IPFP_NOT_CONVERGED or an error. */
+int ipfp_solve_market(ipfp_ctx *ctx, const ipfp_market *mk,
+                      const ipfp_options *opt, ipfp_result *res, void *stream);
+
+/* Solve a market given by a dense surplus Phi (N x M device matrix, dtype
+ * F32 or F64, row stride ld_phi): batch IPFP of eq. 7 / Alg. 1 on the plain
+ * path. opt->path is ignored; opt->compute chooses F32 or F64 storage of K. */
+int ipfp_solve_market_phi(ipfp_ctx *ctx, int64_t N, int64_t M,
+                          ipfp_dtype phi_dtype, const void *Phi,
+                          int64_t ld_phi, const double *n, const double *m,
+                          double sigma, const ipfp_options *opt,
+                          ipfp_result *res, void *stream);
+
+/* ---- resident markets (kept on device between calls) ---------------------- */
+
+/* Pack the market's operands (fused path) or materialise K (plain path),
+ * allocate its scratch and set v to b0 (or 1). The caller's factor and margin
+ * buffers must stay valid until ipfp_market_close. */
+int ipfp_market_open(ipfp_ctx *ctx, const ipfp_market *mk,
+                     const ipfp_options *opt, ipfp_handle **out, void *stream);
+/* Enqueue up to `sweeps` more sweeps (stopping early once converged or at
+ * max_sweeps), then synchronise and report progress. *done is set to 1 when
+ * the solve has finished (converged, or max_sweeps reached and the final
+ * residual recorded). */
+int ipfp_market_run(ipfp_handle *h, int32_t sweeps, int *done, void *stream);
+/* Copy the current (a, b) to caller device buffers and fill `res` (res->a and
+ * res->b are ignored; residual history goes to res->res_hist). */
+int ipfp_market_read(ipfp_handle *h, double *a, double *b, ipfp_result *res,
+                     void *stream);
+void ipfp_market_close(ipfp_handle *h);
+
+/* ---- outputs -------------------------------------------------------------- */
+
+/* Matching masses at `count` requested pairs (eq. 4):
+ * mu_out[i] = exp(Phi_{xs[i], ys[i]} / (2 sigma)) a_{xs[i]} b_{ys[i]}, where
+ * Phi is formed in FP64 from the market's factors as given (in_dtype values,
+ * not the packed compute operands). xs, ys: device int64 indices; a, b:
+ * device FP64 scalings; mu_out: device FP64. Indices out of range give
+ * IPFP_EINVAL (checked on the host before any launch is not possible for
+ * device arrays: the kernel writes NaN for an out-of-range pair and the call
+ * returns IPFP_EINVAL). */
+int ipfp_mu_pairs(ipfp_ctx *ctx, const ipfp_market *mk, const double *a,
+                  const double *b, const int64_t *xs, const int64_t *ys,
+                  int64_t count, double *mu_out, void *stream);
+
+/* The fused path's packed operand of one side: rows [U|Q] (or [V|P])
+ * concatenated, zero-padded to `kpad` columns and rounded to `compute`
+ * (BF16: 2-byte codes; FP8E4M3: 1-byte codes plus one FP32 power-of-two
+ * scale per row written to `scale_out`). `out` is a device buffer of
+ * rows * kpad codes; kpad is returned through *kpad_out (pass out = NULL to
+ * query it). Used to check the packing bit for bit. */
+int ipfp_pack_side(ipfp_ctx *ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
+                   const void *A, const void *B, int64_t ld, ipfp_dtype compute,
+                   void *out, float *scale_out, int64_t *kpad_out,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPFP_H */

@@ -1,0 +1,343 @@
+"""MI355X-native IPFP for Choo-Siow transferable-utility matching markets.
+
+Thin Python binding over libipfp.so (include/ipfp.h). Torch tensors are used
+for device memory and streams only; every step of the sweep runs in the
+library's HIP kernels. Names follow the paper: rows x are candidates with
+margins n, columns y are employers with margins m, sigma is the entropy scale
+(the paper's beta), and the returned scalings are a = sqrt(mu_x0),
+b = sqrt(mu_0y) (Sec. 3.2).
+
+    a, b, info = solve_market(U, Q, V, P, n, m, sigma, tol=1e-6)
+
+solves the market with surplus Phi = U V^T + Q P^T (eq. 8) by the fused
+mini-batch path (Sec. 3.3); ``path="plain"`` materialises K = exp(Phi/2sigma)
+instead (batch IPFP, eq. 7), and ``solve_market_phi`` takes a dense Phi.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+from . import _lib
+
+__all__ = ["IPFPError", "Context", "SolveInfo", "solve_market", "solve_market_phi",
+           "Market", "mu_pairs", "pack_side", "footprint", "library"]
+
+_DT = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "fp8": _lib.FP8E4M3,
+       "fp8e4m3": _lib.FP8E4M3}
+_PATH = {"fused": _lib.PATH_FUSED, "plain": _lib.PATH_PLAIN}
+
+
+def library():
+    return _lib.load()
+
+
+class IPFPError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        msg = library().ipfp_strerror(code).decode()
+        super().__init__(f"{what}: {msg} (code {code})" if what else msg)
+        self.code = code
+
+
+def _check(code: int, what: str) -> int:
+    if code < 0:
+        raise IPFPError(code, what)
+    return code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return _lib.F64
+    if t.dtype == torch.float32:
+        return _lib.F32
+    if t.dtype == torch.bfloat16:
+        return _lib.BF16
+    raise TypeError(f"unsupported factor dtype {t.dtype}")
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    return t
+
+
+class Context:
+    """One library context per device (scratch budget accounting)."""
+
+    _default = {}
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        h = ctypes.c_void_p()
+        _check(library().ipfp_create(ctypes.byref(h), device, budget_bytes), "ipfp_create")
+        self.handle = h
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib._LIB is not None:
+            _lib._LIB.ipfp_destroy(self.handle)
+            self.handle = None
+
+    @classmethod
+    def default(cls, device: int = 0) -> "Context":
+        if device not in cls._default:
+            cls._default[device] = cls(device)
+        return cls._default[device]
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    status: int
+    sweeps: int
+    final_res: float
+    residuals: list
+    setup_ms: float
+    loop_ms: float
+    pass_ms: float
+    pass_launches: int
+    fixups: int
+
+    @property
+    def converged(self) -> bool:
+        return self.status == _lib.OK
+
+
+def _market_struct(U, Q, V, P, n, m, sigma):
+    for t, nm in ((U, "U"), (Q, "Q"), (V, "V"), (P, "P"), (n, "n"), (m, "m")):
+        _dev(t, nm)
+    torch = _torch()
+    if n.dtype != torch.float64 or m.dtype != torch.float64:
+        raise TypeError("margins must be float64")
+    if not (n.is_contiguous() and m.is_contiguous()):
+        raise ValueError("margins must be contiguous")
+    N, d = U.shape
+    M = V.shape[0]
+    if Q.shape != (N, d) or V.shape != (M, d) or P.shape != (M, d):
+        raise ValueError("factor shapes must be U,Q: N x d and V,P: M x d")
+    if n.shape != (N,) or m.shape != (M,):
+        raise ValueError("margin lengths must be N and M")
+    dt = _dtype_code(U)
+    if any(_dtype_code(t) != dt for t in (Q, V, P)):
+        raise TypeError("all factors must share one dtype")
+    for t, nm in ((U, "U"), (Q, "Q"), (V, "V"), (P, "P")):
+        if t.stride(1) != 1:
+            raise ValueError(f"{nm} rows must be contiguous")
+    if U.stride(0) != Q.stride(0) or V.stride(0) != P.stride(0):
+        raise ValueError("U/Q and V/P must share a row stride")
+    mk = _lib.Market()
+    mk.N, mk.M, mk.d = N, M, d
+    mk.in_dtype = dt
+    mk.U, mk.Q, mk.V, mk.P = U.data_ptr(), Q.data_ptr(), V.data_ptr(), P.data_ptr()
+    mk.ld_x, mk.ld_y = U.stride(0), V.stride(0)
+    mk.n, mk.m = n.data_ptr(), m.data_ptr()
+    mk.sigma = float(sigma)
+    return mk
+
+
+def _options(path, compute, tol, max_sweeps, check_every, splits, tile_rows, b0,
+             use_graph, time_passes):
+    o = _lib.Options()
+    library().ipfp_default_options(ctypes.byref(o))
+    o.path = _PATH[path]
+    o.compute = _DT[compute]
+    o.tol = float(tol)
+    o.max_sweeps = int(max_sweeps)
+    o.check_every = int(check_every)
+    o.splits = int(splits)
+    o.tile_rows = int(tile_rows)
+    o.b0 = b0.data_ptr() if b0 is not None else None
+    o.use_graph = int(bool(use_graph))
+    o.time_passes = int(bool(time_passes))
+    return o
+
+
+def _info(code, r, hist):
+    n = min(r.n_res, len(hist))
+    return SolveInfo(code, r.sweeps, r.final_res, [hist[i] for i in range(n)],
+                     r.setup_ms, r.loop_ms, r.pass_ms, r.pass_launches, r.fixups)
+
+
+def solve_market(U, Q, V, P, n, m, sigma, tol=0.0, max_sweeps=100, check_every=1,
+                 path="fused", compute=None, splits=0, tile_rows=0, b0=None,
+                 use_graph=False, time_passes=False, stream=None, ctx=None):
+    """IPFP on the factor market Phi = U V^T + Q P^T; returns (a, b, info)."""
+    torch = _torch()
+    if compute is None:
+        compute = "bf16" if path == "fused" else "f32"
+    mk = _market_struct(U, Q, V, P, n, m, sigma)
+    if b0 is not None:
+        _dev(b0, "b0")
+        if b0.dtype != torch.float64 or b0.shape != (mk.M,):
+            raise ValueError("b0 must be float64 of length M")
+    opt = _options(path, compute, tol, max_sweeps, check_every, splits, tile_rows, b0,
+                   use_graph, time_passes)
+    a = torch.empty(mk.N, dtype=torch.float64, device=U.device)
+    b = torch.empty(mk.M, dtype=torch.float64, device=U.device)
+    hist = (ctypes.c_double * 4096)()
+    r = _lib.Result()
+    r.a, r.b = a.data_ptr(), b.data_ptr()
+    r.res_hist = hist
+    r.res_cap = 4096
+    ctx = ctx or Context.default(U.device.index or 0)
+    code = _check(library().ipfp_solve_market(ctx.handle, ctypes.byref(mk),
+                                              ctypes.byref(opt), ctypes.byref(r),
+                                              _stream_ptr(stream)), "ipfp_solve_market")
+    return a, b, _info(code, r, hist)
+
+
+def solve_market_phi(Phi, n, m, sigma, tol=0.0, max_sweeps=100, check_every=1,
+                     compute="f32", b0=None, use_graph=False, time_passes=False,
+                     stream=None, ctx=None):
+    """Batch IPFP on a dense surplus Phi (N x M, float32 or float64)."""
+    torch = _torch()
+    _dev(Phi, "Phi")
+    _dev(n, "n")
+    _dev(m, "m")
+    N, M = Phi.shape
+    if Phi.stride(1) != 1:
+        raise ValueError("Phi rows must be contiguous")
+    if n.dtype != torch.float64 or m.dtype != torch.float64 or n.shape != (N,) or m.shape != (M,):
+        raise ValueError("margins must be float64 of lengths N and M")
+    opt = _options("plain", compute, tol, max_sweeps, check_every, 0, 0, b0, use_graph,
+                   time_passes)
+    a = torch.empty(N, dtype=torch.float64, device=Phi.device)
+    b = torch.empty(M, dtype=torch.float64, device=Phi.device)
+    hist = (ctypes.c_double * 4096)()
+    r = _lib.Result()
+    r.a, r.b = a.data_ptr(), b.data_ptr()
+    r.res_hist = hist
+    r.res_cap = 4096
+    ctx = ctx or Context.default(Phi.device.index or 0)
+    code = _check(library().ipfp_solve_market_phi(
+        ctx.handle, N, M, _dtype_code(Phi), Phi.data_ptr(), Phi.stride(0), n.data_ptr(),
+        m.data_ptr(), float(sigma), ctypes.byref(opt), ctypes.byref(r),
+        _stream_ptr(stream)), "ipfp_solve_market_phi")
+    return a, b, _info(code, r, hist)
+
+
+class Market:
+    """A market kept resident on the device: open once, run sweeps in batches,
+    read the scalings at any point (``ipfp_market_*``)."""
+
+    def __init__(self, U, Q, V, P, n, m, sigma, tol=0.0, max_sweeps=100,
+                 check_every=1, path="fused", compute=None, splits=0, tile_rows=0,
+                 b0=None, use_graph=False, time_passes=False, stream=None, ctx=None):
+        if compute is None:
+            compute = "bf16" if path == "fused" else "f32"
+        self._keep = (U, Q, V, P, n, m, b0)  # the library reads these buffers
+        self._mk = _market_struct(U, Q, V, P, n, m, sigma)
+        self._opt = _options(path, compute, tol, max_sweeps, check_every, splits,
+                             tile_rows, b0, use_graph, time_passes)
+        self.ctx = ctx or Context.default(U.device.index or 0)
+        self.device = U.device
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(library().ipfp_market_open(self.ctx.handle, ctypes.byref(self._mk),
+                                          ctypes.byref(self._opt), ctypes.byref(h),
+                                          _stream_ptr(stream)), "ipfp_market_open")
+        self.handle = h
+        self.done = False
+
+    def run(self, sweeps: int) -> bool:
+        done = ctypes.c_int(0)
+        _check(library().ipfp_market_run(self.handle, int(sweeps), ctypes.byref(done),
+                                         _stream_ptr(self.stream)), "ipfp_market_run")
+        self.done = bool(done.value)
+        return self.done
+
+    def read(self):
+        torch = _torch()
+        a = torch.empty(self._mk.N, dtype=torch.float64, device=self.device)
+        b = torch.empty(self._mk.M, dtype=torch.float64, device=self.device)
+        hist = (ctypes.c_double * 4096)()
+        r = _lib.Result()
+        r.res_hist = hist
+        r.res_cap = 4096
+        code = _check(library().ipfp_market_read(self.handle, a.data_ptr(), b.data_ptr(),
+                                                 ctypes.byref(r), _stream_ptr(self.stream)),
+                      "ipfp_market_read")
+        return a, b, _info(code, r, hist)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            library().ipfp_market_close(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if _lib._LIB is not None:
+            self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def mu_pairs(U, Q, V, P, sigma, a, b, xs, ys, stream=None, ctx=None):
+    """mu at requested (x, y) pairs: exp(Phi_xy / 2 sigma) a_x b_y (eq. 4)."""
+    torch = _torch()
+    n_dummy = torch.ones(U.shape[0], dtype=torch.float64, device=U.device)
+    m_dummy = torch.ones(V.shape[0], dtype=torch.float64, device=U.device)
+    mk = _market_struct(U, Q, V, P, n_dummy, m_dummy, sigma)
+    xs = xs.to(device=U.device, dtype=torch.int64).contiguous()
+    ys = ys.to(device=U.device, dtype=torch.int64).contiguous()
+    out = torch.empty(xs.numel(), dtype=torch.float64, device=U.device)
+    ctx = ctx or Context.default(U.device.index or 0)
+    _check(library().ipfp_mu_pairs(ctx.handle, ctypes.byref(mk), a.data_ptr(),
+                                   b.data_ptr(), xs.data_ptr(), ys.data_ptr(), xs.numel(),
+                                   out.data_ptr(), _stream_ptr(stream)), "ipfp_mu_pairs")
+    return out
+
+
+def pack_side(A, B, compute="bf16", stream=None, ctx=None):
+    """The fused path's packed operand of one side: (codes, scales or None).
+    BF16 codes come back as int16 (bit patterns), FP8 codes as uint8."""
+    torch = _torch()
+    rows, d = A.shape
+    kpad = ctypes.c_int64()
+    ctx = ctx or Context.default(A.device.index or 0)
+    lib = library()
+    _check(lib.ipfp_pack_side(ctx.handle, rows, d, _dtype_code(A), None, None, A.stride(0),
+                              _DT[compute], None, None, ctypes.byref(kpad), None),
+           "ipfp_pack_side")
+    if compute == "bf16":
+        out = torch.empty((rows, kpad.value), dtype=torch.int16, device=A.device)
+        scale = None
+    else:
+        out = torch.empty((rows, kpad.value), dtype=torch.uint8, device=A.device)
+        scale = torch.empty(rows, dtype=torch.float32, device=A.device)
+    _check(lib.ipfp_pack_side(ctx.handle, rows, d, _dtype_code(A), A.data_ptr(), B.data_ptr(),
+                              A.stride(0), _DT[compute], out.data_ptr(),
+                              scale.data_ptr() if scale is not None else None,
+                              ctypes.byref(kpad), _stream_ptr(stream)), "ipfp_pack_side")
+    return out, scale
+
+
+def footprint(N, M, d, path="fused", compute=None, splits=0, tile_rows=0) -> int:
+    """Scratch bytes a solve of an N x M market with d factors per side needs."""
+    if compute is None:
+        compute = "bf16" if path == "fused" else "f32"
+    mk = _lib.Market()
+    mk.N, mk.M, mk.d = N, M, d
+    mk.in_dtype = _lib.F32
+    mk.U = mk.Q = mk.V = mk.P = 1
+    mk.ld_x = mk.ld_y = d
+    mk.n = mk.m = 1
+    mk.sigma = 1.0
+    opt = _options(path, compute, 0.0, 1, 1, splits, tile_rows, None, False, False)
+    out = ctypes.c_size_t()
+    _check(library().ipfp_footprint(ctypes.byref(mk), ctypes.byref(opt), ctypes.byref(out)),
+           "ipfp_footprint")
+    return out.value

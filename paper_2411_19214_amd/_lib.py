@@ -1,0 +1,107 @@
+"""ctypes declarations of the C ABI in include/ipfp.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libipfp.so")
+
+F64, F32, BF16, FP8E4M3 = 0, 1, 2, 3
+PATH_FUSED, PATH_PLAIN = 0, 1
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, EBUDGET, EHIP, ENONFINITE, ECANCELLED, EBUSY, ENOTFOUND = -1, -2, -3, -4, -5, -6, -7
+
+c_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Market(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("M", ctypes.c_int64), ("d", ctypes.c_int64),
+        ("in_dtype", ctypes.c_int),
+        ("U", ctypes.c_void_p), ("Q", ctypes.c_void_p),
+        ("V", ctypes.c_void_p), ("P", ctypes.c_void_p),
+        ("ld_x", ctypes.c_int64), ("ld_y", ctypes.c_int64),
+        ("n", ctypes.c_void_p), ("m", ctypes.c_void_p),
+        ("sigma", ctypes.c_double),
+    ]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("path", ctypes.c_int), ("compute", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("max_sweeps", ctypes.c_int32), ("check_every", ctypes.c_int32),
+        ("splits", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+        ("b0", ctypes.c_void_p),
+        ("use_graph", ctypes.c_int32), ("time_passes", ctypes.c_int32),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("a", ctypes.c_void_p), ("b", ctypes.c_void_p),
+        ("res_hist", c_dp), ("res_cap", ctypes.c_int32),
+        ("sweeps", ctypes.c_int32), ("n_res", ctypes.c_int32),
+        ("final_res", ctypes.c_double), ("setup_ms", ctypes.c_double),
+        ("loop_ms", ctypes.c_double), ("pass_ms", ctypes.c_double),
+        ("pass_launches", ctypes.c_int32), ("fixups", ctypes.c_int32),
+    ]
+
+
+# name -> (restype, argtypes); every symbol the header declares
+SIGNATURES = {
+    "ipfp_abi_version": (ctypes.c_int, []),
+    "ipfp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "ipfp_default_options": (None, [ctypes.POINTER(Options)]),
+    "ipfp_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                   ctypes.c_size_t]),
+    "ipfp_destroy": (None, [ctypes.c_void_p]),
+    "ipfp_footprint": (ctypes.c_int, [ctypes.POINTER(Market), ctypes.POINTER(Options),
+                                      ctypes.POINTER(ctypes.c_size_t)]),
+    "ipfp_solve_market": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Market),
+                                         ctypes.POINTER(Options), ctypes.POINTER(Result),
+                                         ctypes.c_void_p]),
+    "ipfp_solve_market_phi": (ctypes.c_int, [
+        ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+        ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+        ctypes.POINTER(Options), ctypes.POINTER(Result), ctypes.c_void_p]),
+    "ipfp_market_open": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Market),
+                                        ctypes.POINTER(Options),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
+    "ipfp_market_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int), ctypes.c_void_p]),
+    "ipfp_market_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(Result), ctypes.c_void_p]),
+    "ipfp_market_close": (None, [ctypes.c_void_p]),
+    "ipfp_mu_pairs": (ctypes.c_int, [
+        ctypes.c_void_p, ctypes.POINTER(Market), ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+        ctypes.c_void_p]),
+    "ipfp_pack_side": (ctypes.c_int, [
+        ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+}
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libipfp.so and declare every entry point. Raises when the library
+    has not been built: there is no fallback implementation."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m paper_2411_19214_amd.build`"
+            " (the IPFP kernels exist only as HIP code)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib

@@ -1,0 +1,148 @@
+// Internal declarations shared by the IPFP library's HIP sources (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ipfp.h"
+
+namespace ipfp {
+
+// Device-side control block of one resident market. The sweep loop is driven
+// entirely on the device: every kernel of a sweep reads `done` first and
+// returns at once when the solve has finished, so the host can enqueue (or
+// replay through a graph) more sweeps than remain without changing results.
+struct Ctl {
+  int32_t sweep;        // index i of the state (u^(i), v^(i)) currently held
+  int32_t done;         // 1 once converged, max_sweeps reached or failed
+  int32_t stop_sweep;   // sweep index of the returned state
+  int32_t n_checks;     // residual checks recorded so far
+  int32_t nonfinite;    // 1 if a non-finite intermediate was produced
+  int32_t bad_margin;   // 1 if a margin was not > 0 and finite
+  int32_t fix_rows;     // rows queued for the exact-shift fallback (this pass)
+  int32_t fix_total;    // rows recomputed by the fallback over the solve
+  double last_res;      // most recent recorded residual
+};
+
+// Sweep parameters that are constant for a solve.
+struct SweepParams {
+  double tol;
+  int32_t max_sweeps;
+  int32_t check_every;
+  int32_t hist_cap;     // capacity of the device residual history
+};
+
+// The positive root of w^2 + 2 s w - marg = 0 (eq. 6), evaluated as
+// marg / (s + sqrt(s^2 + marg)) so that it does not cancel for s >> sqrt(marg).
+__device__ __forceinline__ double quad_root(double marg, double s) {
+  if (s > 1e150) return marg / (2.0 * s);
+  return marg / (s + sqrt(s * s + marg));
+}
+
+// True when sweep i's state gets a residual check.
+__device__ __forceinline__ bool is_check(int i, const SweepParams& sp) {
+  return i >= 1 && (i % sp.check_every == 0 || i == sp.max_sweeps);
+}
+
+constexpr int kWave = 64;
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T w = __shfl_xor(v, o, kWave);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// ---- launchers implemented in the .hip sources ----------------------------
+
+// residual / convergence control (control.hip)
+hipError_t launch_check(Ctl* ctl, const double* res_block, int nblocks,
+                        double* hist, SweepParams sp, hipStream_t s);
+hipError_t launch_init_vec(double* v, const double* src, int64_t len,
+                           hipStream_t s);
+hipError_t launch_validate_margins(const double* n, int64_t N, const double* m,
+                                   int64_t M, Ctl* ctl, hipStream_t s);
+hipError_t launch_mu_pairs(const void* U, const void* Q, const void* V,
+                           const void* P, ipfp_dtype dt, int64_t ld_x,
+                           int64_t ld_y, int64_t N, int64_t M, int64_t d,
+                           double sigma, const double* a, const double* b,
+                           const int64_t* xs, const int64_t* ys, int64_t count,
+                           double* mu, int32_t* bad, hipStream_t s);
+
+// plain path (plain.hip)
+hipError_t launch_phi_from_factors(const void* U, const void* Q, const void* V,
+                                   const void* P, ipfp_dtype dt, int64_t ld_x,
+                                   int64_t ld_y, int64_t N, int64_t M,
+                                   int64_t d, void* Kbuf, ipfp_dtype kdt,
+                                   int64_t ldk, hipStream_t s);
+hipError_t launch_materialize(const void* Phi, ipfp_dtype pdt, int64_t ldp,
+                              void* Kbuf, ipfp_dtype kdt, int64_t ldk,
+                              int64_t N, int64_t M, double sigma,
+                              double* cshift, Ctl* ctl, hipStream_t s);
+hipError_t launch_plain_row(const void* K, ipfp_dtype kdt, int64_t ldk,
+                            int64_t N, int64_t M, const double* cshift,
+                            const double* v, const double* n, double* u2,
+                            double* ut, double* res_block, int* nblocks,
+                            Ctl* ctl, hipStream_t s);
+hipError_t launch_plain_col(const void* K, ipfp_dtype kdt, int64_t ldk,
+                            int64_t N, int64_t M, const double* ut, int splits,
+                            double* part, const double* m, double* v, Ctl* ctl,
+                            hipStream_t s);
+int plain_splits(int64_t N, int64_t M, ipfp_dtype kdt);
+
+// fused path (fused.hip)
+struct FusedSide {
+  const void* ops;      // packed operand rows (R x kpad codes)
+  const float* scale;   // FP8: per-row power-of-two scale, else null
+  const float* norm;    // per-row 2-norm of the packed row (FP32)
+  int64_t rows;
+};
+int64_t fused_kpad(int64_t d, ipfp_dtype compute);
+hipError_t launch_pack(const void* A, const void* B, ipfp_dtype in_dt,
+                       int64_t ld, int64_t rows, int64_t d, ipfp_dtype compute,
+                       int64_t kpad, void* out, float* scale, float* norm,
+                       Ctl* ctl, hipStream_t s);
+
+struct FusedPass {
+  FusedSide out, red;       // output side (its scalings are updated) and
+                            // reduced side (summed over)
+  ipfp_dtype compute;
+  int64_t kpad;
+  float c;                  // log2(e) / (2 sigma)
+  const float* bias;        // red.rows: log2 of the reduced side's scaling
+  float* shift;             // out.rows: additive shift of the surplus
+  const double* marg;       // out.rows margins
+  float* lw_new;            // out.rows: log2 of the updated scaling
+  double* part;             // splits x out.rows partial sums
+  double* res_block;        // per-combine-block residual maxima
+  int32_t* fix_list;        // out.rows
+  int splits;
+  int tile_rows;            // requested output rows per workgroup
+  bool residual;            // compute the row residual of the old scaling
+};
+hipError_t launch_fused_pass(const FusedPass& fp, Ctl* ctl, hipStream_t s);
+hipError_t launch_fused_combine(const FusedPass& fp, double* w2, int dbuf,
+                                Ctl* ctl, int* nblocks, hipStream_t s);
+hipError_t launch_fused_fixup(const FusedPass& fp, double* w2, int dbuf,
+                              double* res_slot, Ctl* ctl, hipStream_t s);
+hipError_t launch_initial_shift(const FusedSide& out, const FusedSide& red,
+                                float c, double lscale, const double* wmax_src,
+                                int64_t wmax_len, float* shift, float* tmp,
+                                hipStream_t s);
+hipError_t launch_log2_vec(const double* w, float* lw, int64_t len,
+                           hipStream_t s);
+int fused_auto_splits(int64_t R, int64_t L, int rows_per_wg);
+int fused_rows_per_wg(int64_t kpad, ipfp_dtype compute, int tile_rows);
+int fused_fixup_blocks();
+
+}  // namespace ipfp

@@ -1,0 +1,152 @@
+// Convergence control, small vector kernels and the matching-mass output.
+#include <math.h>
+
+#include "common.h"
+
+namespace ipfp {
+
+// One workgroup: reduce the residual maxima of the row pass that just ran
+// (they belong to state i = ctl->sweep), record them at check sweeps, decide
+// whether the solve stops at state i, and otherwise advance to state i + 1.
+// The residual of state i is available here because the row pass of sweep
+// i + 1 computes K v^(i) anyway; u^(i) is kept in the other half of a double
+// buffer, so stopping at i returns exactly (u^(i), v^(i)).
+__global__ void __launch_bounds__(256) k_check(Ctl* ctl, const double* res_block,
+                                               int nblocks, double* hist,
+                                               SweepParams sp) {
+  __shared__ double red[256];
+  if (ctl->done) return;
+  const int i = ctl->sweep;
+  const bool chk = is_check(i, sp);
+  double r = 0.0;
+  if (chk) {
+    for (int k = threadIdx.x; k < nblocks; k += blockDim.x) {
+      double x = res_block[k];
+      // NaN compares false: keep it visible
+      r = (x > r || x != x) ? x : r;
+    }
+  }
+  red[threadIdx.x] = r;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      double a = red[threadIdx.x], b = red[threadIdx.x + o];
+      red[threadIdx.x] = (b > a || b != b) ? b : a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (ctl->nonfinite || ctl->bad_margin) {
+    ctl->done = 1;
+    ctl->stop_sweep = i;
+    return;
+  }
+  if (chk) {
+    r = red[0];
+    if (ctl->n_checks < sp.hist_cap) hist[ctl->n_checks] = r;
+    ctl->n_checks += 1;
+    ctl->last_res = r;
+    if (r != r) ctl->nonfinite = 1;
+    if (r < sp.tol || i >= sp.max_sweeps || r != r) {
+      ctl->done = 1;
+      ctl->stop_sweep = i;
+      return;
+    }
+  }
+  ctl->sweep = i + 1;
+}
+
+hipError_t launch_check(Ctl* ctl, const double* res_block, int nblocks,
+                        double* hist, SweepParams sp, hipStream_t s) {
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, s, ctl, res_block, nblocks,
+                     hist, sp);
+  return hipGetLastError();
+}
+
+__global__ void k_init_vec(double* v, const double* src, int64_t len) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) v[i] = src ? src[i] : 1.0;
+}
+
+hipError_t launch_init_vec(double* v, const double* src, int64_t len,
+                           hipStream_t s) {
+  int64_t blocks = (len + 255) / 256;
+  hipLaunchKernelGGL(k_init_vec, dim3((unsigned)blocks), dim3(256), 0, s, v, src,
+                     len);
+  return hipGetLastError();
+}
+
+__global__ void k_validate(const double* a, int64_t len, Ctl* ctl) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) {
+    double x = a[i];
+    if (!(x > 0.0) || !(x < INFINITY)) atomicOr(&ctl->bad_margin, 1);
+  }
+}
+
+hipError_t launch_validate_margins(const double* n, int64_t N, const double* m,
+                                   int64_t M, Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
+                     s, n, N, ctl);
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)((M + 255) / 256)), dim3(256), 0,
+                     s, m, M, ctl);
+  return hipGetLastError();
+}
+
+template <typename T>
+__device__ __forceinline__ double ld_as_double(const void* p, int64_t i) {
+  return (double)static_cast<const T*>(p)[i];
+}
+
+__device__ __forceinline__ double ld_elem(const void* p, int64_t i,
+                                          ipfp_dtype dt) {
+  switch (dt) {
+    case IPFP_F64:
+      return static_cast<const double*>(p)[i];
+    case IPFP_F32:
+      return (double)static_cast<const float*>(p)[i];
+    default: {  // BF16 codes
+      uint32_t bits = (uint32_t)static_cast<const uint16_t*>(p)[i] << 16;
+      return (double)__uint_as_float(bits);
+    }
+  }
+}
+
+// mu_xy = exp(Phi_xy / 2 sigma) a_x b_y at requested pairs (eq. 4), with the
+// surplus formed in FP64 from the factors as given.
+__global__ void k_mu_pairs(const void* U, const void* Q, const void* V,
+                           const void* P, ipfp_dtype dt, int64_t ld_x,
+                           int64_t ld_y, int64_t N, int64_t M, int64_t d,
+                           double sigma, const double* a, const double* b,
+                           const int64_t* xs, const int64_t* ys, int64_t count,
+                           double* mu, int32_t* bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  int64_t x = xs[i], y = ys[i];
+  if (x < 0 || x >= N || y < 0 || y >= M) {
+    mu[i] = NAN;
+    atomicOr(bad, 1);
+    return;
+  }
+  double phi = 0.0;
+  for (int64_t k = 0; k < d; ++k) {
+    phi = fma(ld_elem(U, x * ld_x + k, dt), ld_elem(V, y * ld_y + k, dt), phi);
+    phi = fma(ld_elem(Q, x * ld_x + k, dt), ld_elem(P, y * ld_y + k, dt), phi);
+  }
+  mu[i] = exp(phi / (2.0 * sigma)) * a[x] * b[y];
+}
+
+hipError_t launch_mu_pairs(const void* U, const void* Q, const void* V,
+                           const void* P, ipfp_dtype dt, int64_t ld_x,
+                           int64_t ld_y, int64_t N, int64_t M, int64_t d,
+                           double sigma, const double* a, const double* b,
+                           const int64_t* xs, const int64_t* ys, int64_t count,
+                           double* mu, int32_t* bad, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mu_pairs, dim3((unsigned)((count + 255) / 256)), dim3(256),
+                     0, s, U, Q, V, P, dt, ld_x, ld_y, N, M, d, sigma, a, b, xs,
+                     ys, count, mu, bad);
+  return hipGetLastError();
+}
+
+}  // namespace ipfp

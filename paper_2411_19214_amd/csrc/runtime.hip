@@ -1,0 +1,691 @@
+// C ABI: contexts, resident markets, the device-driven sweep loop and the
+// one-call solves. Every sweep is a fixed sequence of kernels on the caller's
+// stream; the only host/device synchronisation is a 64-byte read of the
+// control block after each batch of enqueued sweeps.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+using namespace ipfp;
+
+#define HIPCHK(expr)                         \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return IPFP_EHIP;  \
+  } while (0)
+
+struct ipfp_ctx {
+  int device;
+  size_t budget;
+  size_t used;
+  std::mutex mu;
+};
+
+namespace {
+
+constexpr int kHistCap = 4096;  // device residual history entries per market
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Carves one device allocation into aligned sub-buffers.
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+size_t dtype_size(ipfp_dtype t) {
+  switch (t) {
+    case IPFP_F64: return 8;
+    case IPFP_F32: return 4;
+    case IPFP_BF16: return 2;
+    default: return 1;
+  }
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+
+struct ipfp_handle {
+  ipfp_ctx* ctx = nullptr;
+  ipfp_market mk{};
+  ipfp_options opt{};
+  bool plain = false;
+  int64_t N = 0, M = 0;
+  size_t bytes = 0;
+  char* mem = nullptr;
+  // shared state
+  Ctl* ctl = nullptr;
+  double* hist = nullptr;
+  double* res_block = nullptr;   // row residual maxima (combine + fixup slots)
+  double* res_dummy = nullptr;   // column side writes its (unused) maxima here
+  double* u2 = nullptr;          // 2 x N double buffer
+  double* v = nullptr;           // M
+  int nres_row = 0;              // entries of res_block the check reduces
+  // plain path
+  ipfp_dtype kdt = IPFP_F32;
+  void* K = nullptr;
+  int64_t ldk = 0;
+  double* cshift = nullptr;
+  double* ut = nullptr;
+  double* part = nullptr;
+  int psplits = 1;
+  // fused path
+  int64_t kpad = 0;
+  void *xop = nullptr, *yop = nullptr;
+  float *xscale = nullptr, *yscale = nullptr, *xnorm = nullptr, *ynorm = nullptr;
+  float *xshift = nullptr, *yshift = nullptr, *lu = nullptr, *lv = nullptr;
+  double *xpart = nullptr, *ypart = nullptr;
+  int32_t *xfix = nullptr, *yfix = nullptr;
+  float* tmp = nullptr;
+  FusedPass rowp{}, colp{};
+  int row_combine_blocks = 0, col_combine_blocks = 0;
+  // loop state
+  int units = 0;                 // sweep units enqueued so far
+  Ctl* host_ctl = nullptr;       // pinned mirror
+  hipGraphExec_t graph = nullptr;
+  int graph_units = 0;
+  hipStream_t cap_stream = nullptr;
+  std::vector<hipEvent_t> evs;   // pass timing events (pairs)
+  double pass_ms = 0.0;
+  int pass_launches = 0;
+  double loop_ms = 0.0;
+  double setup_ms = 0.0;
+  float sigma_c = 0.f;
+};
+
+// ---- sizes -------------------------------------------------------------------
+
+static void layout(ipfp_handle* h, Carver& cv) {
+  const int64_t N = h->N, M = h->M;
+  h->ctl = cv.take<Ctl>(1);
+  h->hist = cv.take<double>(kHistCap);
+  h->u2 = cv.take<double>(2 * N);
+  h->v = cv.take<double>(M);
+  if (h->plain) {
+    const int64_t vn = h->kdt == IPFP_F64 ? 2 : 4;
+    h->ldk = align_up((size_t)M, 64);
+    (void)vn;
+    h->K = cv.take<char>((size_t)N * h->ldk * dtype_size(h->kdt));
+    h->cshift = cv.take<double>(N);
+    h->ut = cv.take<double>(N);
+    h->psplits = plain_splits(N, M, h->kdt);
+    h->part = cv.take<double>((size_t)h->psplits * M);
+    h->nres_row = (int)((N + 15) / 16);
+    h->res_block = cv.take<double>(h->nres_row);
+  } else {
+    const ipfp_dtype cd = h->opt.compute;
+    const size_t es = cd == IPFP_FP8E4M3 ? 1 : 2;
+    h->kpad = fused_kpad(h->mk.d, cd);
+    h->xop = cv.take<char>((size_t)N * h->kpad * es);
+    h->yop = cv.take<char>((size_t)M * h->kpad * es);
+    h->xscale = cv.take<float>(N);
+    h->yscale = cv.take<float>(M);
+    h->xnorm = cv.take<float>(N);
+    h->ynorm = cv.take<float>(M);
+    h->xshift = cv.take<float>(N);
+    h->yshift = cv.take<float>(M);
+    h->lu = cv.take<float>(N);
+    h->lv = cv.take<float>(M);
+    const int tr = h->opt.tile_rows > 0 ? h->opt.tile_rows : 512;
+    const int rx = fused_rows_per_wg(h->kpad, cd, tr);
+    int sx = h->opt.splits > 0 ? h->opt.splits : fused_auto_splits(N, M, rx);
+    int sy = h->opt.splits > 0 ? h->opt.splits : fused_auto_splits(M, N, rx);
+    h->xpart = cv.take<double>((size_t)sx * N);
+    h->ypart = cv.take<double>((size_t)sy * M);
+    h->xfix = cv.take<int32_t>(N);
+    h->yfix = cv.take<int32_t>(M);
+    h->tmp = cv.take<float>(4);
+    h->row_combine_blocks = (int)((N + 255) / 256);
+    h->col_combine_blocks = (int)((M + 255) / 256);
+    h->nres_row = h->row_combine_blocks + fused_fixup_blocks();
+    h->res_block = cv.take<double>(h->nres_row);
+    h->res_dummy = cv.take<double>(h->col_combine_blocks + fused_fixup_blocks());
+    h->rowp.splits = sx;
+    h->colp.splits = sy;
+    h->rowp.tile_rows = h->colp.tile_rows = tr;
+  }
+}
+
+static int validate(const ipfp_market* mk, const ipfp_options* opt, bool factors) {
+  if (!mk || !opt) return IPFP_EINVAL;
+  if (mk->N < 1 || mk->M < 1) return IPFP_EINVAL;
+  if (mk->N > INT32_MAX || mk->M > INT32_MAX) return IPFP_EINVAL;
+  if (!(mk->sigma > 0.0) || !(mk->sigma < INFINITY)) return IPFP_EINVAL;
+  if (!mk->n || !mk->m) return IPFP_EINVAL;
+  if (opt->max_sweeps < 1 || opt->check_every < 1) return IPFP_EINVAL;
+  if (!(opt->tol >= 0.0)) return IPFP_EINVAL;
+  if (opt->splits < 0 || opt->splits > 256) return IPFP_EINVAL;
+  if (factors) {
+    if (mk->d < 1 || mk->d > 256) return IPFP_EINVAL;
+    if (!mk->U || !mk->Q || !mk->V || !mk->P) return IPFP_EINVAL;
+    if (mk->ld_x < mk->d || mk->ld_y < mk->d) return IPFP_EINVAL;
+    if (mk->in_dtype != IPFP_F64 && mk->in_dtype != IPFP_F32 &&
+        mk->in_dtype != IPFP_BF16)
+      return IPFP_EINVAL;
+  }
+  if (opt->path == IPFP_PATH_PLAIN) {
+    if (opt->compute != IPFP_F32 && opt->compute != IPFP_F64) return IPFP_EINVAL;
+  } else if (opt->path == IPFP_PATH_FUSED) {
+    if (opt->compute != IPFP_BF16 && opt->compute != IPFP_FP8E4M3) return IPFP_EINVAL;
+    if (mk->d > 128) return IPFP_EINVAL;
+    if (opt->tile_rows != 0 && opt->tile_rows != 128 && opt->tile_rows != 256 &&
+        opt->tile_rows != 512)
+      return IPFP_EINVAL;
+  } else {
+    return IPFP_EINVAL;
+  }
+  return IPFP_OK;
+}
+
+// ---- sweep units ---------------------------------------------------------------
+
+static SweepParams sweep_params(const ipfp_handle* h) {
+  SweepParams sp;
+  sp.tol = h->opt.tol;
+  sp.max_sweeps = h->opt.max_sweeps;
+  sp.check_every = h->opt.check_every;
+  sp.hist_cap = kHistCap;
+  return sp;
+}
+
+static hipError_t timed(ipfp_handle* h, bool timing, hipStream_t s,
+                        hipError_t (*fn)(const FusedPass&, Ctl*, hipStream_t),
+                        const FusedPass& fp) {
+  if (!timing) return fn(fp, h->ctl, s);
+  hipEvent_t a, b;
+  hipEventCreate(&a);
+  hipEventCreate(&b);
+  hipEventRecord(a, s);
+  hipError_t e = fn(fp, h->ctl, s);
+  hipEventRecord(b, s);
+  h->evs.push_back(a);
+  h->evs.push_back(b);
+  return e;
+}
+
+// One sweep unit: the row half-sweep for the current state, the convergence
+// check, then the column half-sweep (skipped on the device once done).
+static hipError_t enqueue_unit(ipfp_handle* h, hipStream_t s, bool timing) {
+  hipError_t e;
+  const SweepParams sp = sweep_params(h);
+  if (h->plain) {
+    int nb = 0;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timing) {
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      hipEventRecord(a, s);
+    }
+    e = launch_plain_row(h->K, h->kdt, h->ldk, h->N, h->M, h->cshift, h->v,
+                         h->mk.n, h->u2, h->ut, h->res_block, &nb, h->ctl, s);
+    if (timing) {
+      hipEventRecord(b, s);
+      h->evs.push_back(a);
+      h->evs.push_back(b);
+    }
+    if (e != hipSuccess) return e;
+    e = launch_check(h->ctl, h->res_block, nb, h->hist, sp, s);
+    if (e != hipSuccess) return e;
+    if (timing) {
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      hipEventRecord(a, s);
+    }
+    e = launch_plain_col(h->K, h->kdt, h->ldk, h->N, h->M, h->ut, h->psplits,
+                         h->part, h->mk.m, h->v, h->ctl, s);
+    if (timing) {
+      hipEventRecord(b, s);
+      h->evs.push_back(a);
+      h->evs.push_back(b);
+    }
+    return e;
+  }
+  int nb = 0;
+  e = timed(h, timing, s, launch_fused_pass, h->rowp);
+  if (e != hipSuccess) return e;
+  e = launch_fused_combine(h->rowp, h->u2, 1, h->ctl, &nb, s);
+  if (e != hipSuccess) return e;
+  e = launch_fused_fixup(h->rowp, h->u2, 1, h->res_block + h->row_combine_blocks,
+                         h->ctl, s);
+  if (e != hipSuccess) return e;
+  e = launch_check(h->ctl, h->res_block, h->nres_row, h->hist, sp, s);
+  if (e != hipSuccess) return e;
+  e = timed(h, timing, s, launch_fused_pass, h->colp);
+  if (e != hipSuccess) return e;
+  e = launch_fused_combine(h->colp, h->v, 0, h->ctl, &nb, s);
+  if (e != hipSuccess) return e;
+  return launch_fused_fixup(h->colp, h->v, 0,
+                            h->res_dummy + h->col_combine_blocks, h->ctl, s);
+}
+
+static int read_ctl(ipfp_handle* h, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(h->host_ctl, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return IPFP_OK;
+}
+
+static void collect_events(ipfp_handle* h) {
+  for (size_t k = 0; k + 1 < h->evs.size(); k += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->evs[k], h->evs[k + 1]) == hipSuccess) {
+      h->pass_ms += ms;
+      h->pass_launches += 1;
+    }
+    hipEventDestroy(h->evs[k]);
+    hipEventDestroy(h->evs[k + 1]);
+  }
+  h->evs.clear();
+}
+
+// ---- C ABI -------------------------------------------------------------------
+
+extern "C" {
+
+int ipfp_abi_version(void) { return IPFP_ABI_VERSION; }
+
+const char* ipfp_strerror(int code) {
+  switch (code) {
+    case IPFP_OK: return "ok";
+    case IPFP_NOT_CONVERGED: return "tolerance not reached within max_sweeps";
+    case IPFP_EINVAL: return "invalid argument";
+    case IPFP_EBUDGET: return "scratch memory exceeds the context budget";
+    case IPFP_EHIP: return "HIP runtime error";
+    case IPFP_ENONFINITE: return "non-finite input or intermediate value";
+    case IPFP_ECANCELLED: return "request cancelled";
+    case IPFP_EBUSY: return "request not finished";
+    case IPFP_ENOTFOUND: return "unknown ticket";
+    default: return "unknown error code";
+  }
+}
+
+void ipfp_default_options(ipfp_options* opt) {
+  memset(opt, 0, sizeof(*opt));
+  opt->path = IPFP_PATH_FUSED;
+  opt->compute = IPFP_BF16;
+  opt->tol = 0.0;
+  opt->max_sweeps = 100;
+  opt->check_every = 1;
+}
+
+int ipfp_create(ipfp_ctx** out, int hip_device, size_t hbm_budget_bytes) {
+  if (!out) return IPFP_EINVAL;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n)
+    return IPFP_EINVAL;
+  ipfp_ctx* c = new ipfp_ctx;
+  c->device = hip_device;
+  c->budget = hbm_budget_bytes;
+  c->used = 0;
+  *out = c;
+  return IPFP_OK;
+}
+
+void ipfp_destroy(ipfp_ctx* ctx) { delete ctx; }
+
+static int footprint_impl(const ipfp_market* mk, const ipfp_options* opt,
+                          bool plain, size_t* bytes) {
+  ipfp_handle h;
+  h.mk = *mk;
+  h.opt = *opt;
+  h.plain = plain;
+  h.N = mk->N;
+  h.M = mk->M;
+  h.kdt = opt->compute == IPFP_F64 ? IPFP_F64 : IPFP_F32;
+  Carver cv;
+  layout(&h, cv);
+  *bytes = align_up(cv.off, 256);
+  return IPFP_OK;
+}
+
+int ipfp_footprint(const ipfp_market* mk, const ipfp_options* opt,
+                   size_t* bytes_out) {
+  if (!bytes_out) return IPFP_EINVAL;
+  int rc = validate(mk, opt, true);
+  if (rc != IPFP_OK) return rc;
+  return footprint_impl(mk, opt, opt->path == IPFP_PATH_PLAIN, bytes_out);
+}
+
+static int reserve(ipfp_ctx* ctx, size_t bytes) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (ctx->budget && ctx->used + bytes > ctx->budget) return IPFP_EBUDGET;
+  ctx->used += bytes;
+  return IPFP_OK;
+}
+
+static void release(ipfp_ctx* ctx, size_t bytes) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->used -= bytes;
+}
+
+static void destroy_handle(ipfp_handle* h) {
+  if (!h) return;
+  collect_events(h);
+  if (h->graph) hipGraphExecDestroy(h->graph);
+  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+  if (h->host_ctl) hipHostFree(h->host_ctl);
+  if (h->mem) hipFree(h->mem);
+  if (h->ctx && h->bytes) release(h->ctx, h->bytes);
+  delete h;
+}
+
+// Opens a market: explicit Phi (phi != null) or factors.
+static int open_impl(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* opt,
+                     const void* phi, ipfp_dtype phi_dt, int64_t ld_phi,
+                     ipfp_handle** out, hipStream_t s) {
+  *out = nullptr;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IPFP_EHIP;
+  const double t0 = now_ms();
+  ipfp_handle* h = new ipfp_handle;
+  h->ctx = ctx;
+  h->mk = *mk;
+  h->opt = *opt;
+  h->plain = phi != nullptr || opt->path == IPFP_PATH_PLAIN;
+  h->N = mk->N;
+  h->M = mk->M;
+  h->kdt = opt->compute == IPFP_F64 ? IPFP_F64 : IPFP_F32;
+  Carver cv;
+  layout(h, cv);
+  const size_t bytes = align_up(cv.off, 256);
+  int rc = reserve(ctx, bytes);
+  if (rc != IPFP_OK) {
+    delete h;
+    return rc;
+  }
+  h->bytes = bytes;
+  if (hipMalloc((void**)&h->mem, bytes) != hipSuccess) {
+    h->mem = nullptr;
+    destroy_handle(h);
+    return IPFP_EBUDGET;
+  }
+  if (hipHostMalloc((void**)&h->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    h->host_ctl = nullptr;
+    destroy_handle(h);
+    return IPFP_EHIP;
+  }
+  Carver real;
+  real.base = h->mem;
+  layout(h, real);
+
+  auto fail = [&](int code) {
+    destroy_handle(h);
+    return code;
+  };
+  if (hipMemsetAsync(h->ctl, 0, sizeof(Ctl), s) != hipSuccess) return fail(IPFP_EHIP);
+  if (launch_validate_margins(mk->n, h->N, mk->m, h->M, h->ctl, s) != hipSuccess)
+    return fail(IPFP_EHIP);
+  if (launch_init_vec(h->u2, nullptr, 2 * h->N, s) != hipSuccess) return fail(IPFP_EHIP);
+  if (launch_init_vec(h->v, opt->b0, h->M, s) != hipSuccess) return fail(IPFP_EHIP);
+
+  if (h->plain) {
+    hipError_t e;
+    if (phi) {
+      e = launch_materialize(phi, phi_dt, ld_phi, h->K, h->kdt, h->ldk, h->N, h->M,
+                             mk->sigma, h->cshift, h->ctl, s);
+    } else {
+      e = launch_phi_from_factors(mk->U, mk->Q, mk->V, mk->P, mk->in_dtype, mk->ld_x,
+                                  mk->ld_y, h->N, h->M, mk->d, h->K, h->kdt, h->ldk, s);
+      if (e == hipSuccess)
+        e = launch_materialize(h->K, h->kdt, h->ldk, h->K, h->kdt, h->ldk, h->N, h->M,
+                               mk->sigma, h->cshift, h->ctl, s);
+    }
+    if (e != hipSuccess) return fail(IPFP_EHIP);
+  } else {
+    const ipfp_dtype cd = opt->compute;
+    const float c = (float)(1.4426950408889634 / (2.0 * mk->sigma));
+    h->sigma_c = c;
+    if (launch_pack(mk->U, mk->Q, mk->in_dtype, mk->ld_x, h->N, mk->d, cd, h->kpad,
+                    h->xop, h->xscale, h->xnorm, h->ctl, s) != hipSuccess ||
+        launch_pack(mk->V, mk->P, mk->in_dtype, mk->ld_y, h->M, mk->d, cd, h->kpad,
+                    h->yop, h->yscale, h->ynorm, h->ctl, s) != hipSuccess)
+      return fail(IPFP_EHIP);
+    FusedSide X{h->xop, cd == IPFP_FP8E4M3 ? h->xscale : nullptr, h->xnorm, h->N};
+    FusedSide Y{h->yop, cd == IPFP_FP8E4M3 ? h->yscale : nullptr, h->ynorm, h->M};
+    FusedPass& r = h->rowp;
+    r.out = X; r.red = Y; r.compute = cd; r.kpad = h->kpad; r.c = c;
+    r.bias = h->lv; r.shift = h->xshift; r.marg = mk->n; r.lw_new = h->lu;
+    r.part = h->xpart; r.res_block = h->res_block; r.fix_list = h->xfix;
+    r.residual = true;
+    FusedPass& q = h->colp;
+    q.out = Y; q.red = X; q.compute = cd; q.kpad = h->kpad; q.c = c;
+    q.bias = h->lu; q.shift = h->yshift; q.marg = mk->m; q.lw_new = h->lv;
+    q.part = h->ypart; q.res_block = h->res_dummy; q.fix_list = h->yfix;
+    q.residual = false;
+    // first-pass shifts from the Cauchy-Schwarz bound: row side against the
+    // initial v, column side against u <= sqrt(max n)
+    if (launch_log2_vec(h->v, h->lv, h->M, s) != hipSuccess ||
+        launch_initial_shift(X, Y, c, 1.0, h->v, h->M, h->xshift, h->tmp, s) != hipSuccess ||
+        launch_initial_shift(Y, X, c, 0.5, mk->n, h->N, h->yshift, h->tmp + 2, s) != hipSuccess)
+      return fail(IPFP_EHIP);
+  }
+  if (read_ctl(h, s) != IPFP_OK) return fail(IPFP_EHIP);
+  if (h->host_ctl->bad_margin) return fail(IPFP_EINVAL);
+  if (h->host_ctl->nonfinite) return fail(IPFP_ENONFINITE);
+  h->setup_ms = now_ms() - t0;
+  *out = h;
+  return IPFP_OK;
+}
+
+int ipfp_market_open(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* opt,
+                     ipfp_handle** out, void* stream) {
+  if (!ctx || !out) return IPFP_EINVAL;
+  int rc = validate(mk, opt, true);
+  if (rc != IPFP_OK) return rc;
+  return open_impl(ctx, mk, opt, nullptr, IPFP_F32, 0, out, (hipStream_t)stream);
+}
+
+static int run_impl(ipfp_handle* h, int32_t sweeps, int* done, hipStream_t s) {
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return IPFP_EHIP;
+  const int total = h->opt.max_sweeps + 1;  // +1: final residual row pass
+  int todo = std::min(sweeps, total - h->units);
+  const bool timing = h->opt.time_passes != 0;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  if (h->opt.use_graph && !timing && todo > 0) {
+    const int G = std::max(1, std::min(h->opt.check_every, 16));
+    if (!h->graph && todo >= G) {
+      if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+      hipGraph_t g;
+      HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < G; ++k) {
+        if (enqueue_unit(h, h->cap_stream, false) != hipSuccess) {
+          hipStreamEndCapture(h->cap_stream, &g);
+          return IPFP_EHIP;
+        }
+      }
+      HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
+      HIPCHK(hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0));
+      hipGraphDestroy(g);
+      h->graph_units = G;
+    }
+    while (h->graph && todo >= h->graph_units) {
+      HIPCHK(hipGraphLaunch(h->graph, s));
+      todo -= h->graph_units;
+      h->units += h->graph_units;
+    }
+  }
+  for (; todo > 0; --todo) {
+    if (enqueue_unit(h, s, timing) != hipSuccess) return IPFP_EHIP;
+    h->units += 1;
+  }
+  HIPCHK(hipEventRecord(e1, s));
+  int rc = read_ctl(h, s);
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) h->loop_ms += ms;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  collect_events(h);
+  if (rc != IPFP_OK) return rc;
+  if (done) *done = h->host_ctl->done || h->units >= total;
+  if (h->host_ctl->nonfinite) return IPFP_ENONFINITE;
+  return IPFP_OK;
+}
+
+int ipfp_market_run(ipfp_handle* h, int32_t sweeps, int* done, void* stream) {
+  if (!h || sweeps < 0) return IPFP_EINVAL;
+  return run_impl(h, sweeps, done, (hipStream_t)stream);
+}
+
+int ipfp_market_read(ipfp_handle* h, double* a, double* b, ipfp_result* res,
+                     void* stream) {
+  if (!h) return IPFP_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return IPFP_EHIP;
+  int rc = read_ctl(h, s);
+  if (rc != IPFP_OK) return rc;
+  const Ctl c = *h->host_ctl;
+  // the state held is c.sweep until the solve stops; then c.stop_sweep
+  const int state = c.done ? c.stop_sweep : c.sweep;
+  const double* u = h->u2 + (int64_t)(state & 1) * h->N;
+  if (a) HIPCHK(hipMemcpyAsync(a, u, h->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (b) HIPCHK(hipMemcpyAsync(b, h->v, h->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (res) {
+    res->sweeps = state;
+    res->n_res = c.n_checks;
+    res->final_res = c.n_checks ? c.last_res : NAN;
+    res->setup_ms = h->setup_ms;
+    res->loop_ms = h->loop_ms;
+    res->pass_ms = h->pass_ms;
+    res->pass_launches = h->pass_launches;
+    res->fixups = c.fix_total;
+    const int ncopy = std::min(std::min(c.n_checks, res->res_cap), kHistCap);
+    if (res->res_hist && ncopy > 0)
+      HIPCHK(hipMemcpyAsync(res->res_hist, h->hist, ncopy * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (c.nonfinite) return IPFP_ENONFINITE;
+  if (h->opt.tol > 0.0 && c.done && !(c.last_res < h->opt.tol)) return IPFP_NOT_CONVERGED;
+  return IPFP_OK;
+}
+
+void ipfp_market_close(ipfp_handle* h) { destroy_handle(h); }
+
+static int solve_handle(ipfp_handle* h, ipfp_result* res, hipStream_t s) {
+  int done = 0;
+  const int chunk = std::max(h->opt.check_every, 8);
+  while (!done) {
+    int rc = run_impl(h, chunk, &done, s);
+    if (rc != IPFP_OK) return rc;
+  }
+  return ipfp_market_read(h, res->a, res->b, res, s);
+}
+
+int ipfp_solve_market(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* opt,
+                      ipfp_result* res, void* stream) {
+  if (!ctx || !res || !res->a || !res->b) return IPFP_EINVAL;
+  int rc = validate(mk, opt, true);
+  if (rc != IPFP_OK) return rc;
+  ipfp_handle* h = nullptr;
+  rc = open_impl(ctx, mk, opt, nullptr, IPFP_F32, 0, &h, (hipStream_t)stream);
+  if (rc != IPFP_OK) return rc;
+  rc = solve_handle(h, res, (hipStream_t)stream);
+  destroy_handle(h);
+  return rc;
+}
+
+int ipfp_solve_market_phi(ipfp_ctx* ctx, int64_t N, int64_t M, ipfp_dtype phi_dtype,
+                          const void* Phi, int64_t ld_phi, const double* n,
+                          const double* m, double sigma, const ipfp_options* opt,
+                          ipfp_result* res, void* stream) {
+  if (!ctx || !res || !res->a || !res->b || !Phi || !opt) return IPFP_EINVAL;
+  if (phi_dtype != IPFP_F32 && phi_dtype != IPFP_F64) return IPFP_EINVAL;
+  if (ld_phi < M) return IPFP_EINVAL;
+  ipfp_market mk{};
+  mk.N = N;
+  mk.M = M;
+  mk.d = 1;
+  mk.n = n;
+  mk.m = m;
+  mk.sigma = sigma;
+  ipfp_options o = *opt;
+  o.path = IPFP_PATH_PLAIN;
+  if (o.compute != IPFP_F64) o.compute = IPFP_F32;
+  int rc = validate(&mk, &o, false);
+  if (rc != IPFP_OK) return rc;
+  ipfp_handle* h = nullptr;
+  rc = open_impl(ctx, &mk, &o, Phi, phi_dtype, ld_phi, &h, (hipStream_t)stream);
+  if (rc != IPFP_OK) return rc;
+  rc = solve_handle(h, res, (hipStream_t)stream);
+  destroy_handle(h);
+  return rc;
+}
+
+int ipfp_mu_pairs(ipfp_ctx* ctx, const ipfp_market* mk, const double* a,
+                  const double* b, const int64_t* xs, const int64_t* ys,
+                  int64_t count, double* mu_out, void* stream) {
+  if (!ctx || !mk || !a || !b || (count > 0 && (!xs || !ys || !mu_out)) || count < 0)
+    return IPFP_EINVAL;
+  if (!mk->U || !mk->Q || !mk->V || !mk->P || mk->d < 1 || !(mk->sigma > 0.0))
+    return IPFP_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IPFP_EHIP;
+  int32_t* bad = nullptr;
+  HIPCHK(hipMalloc((void**)&bad, sizeof(int32_t)));
+  int rc = IPFP_OK;
+  int32_t hb = 0;
+  if (hipMemsetAsync(bad, 0, sizeof(int32_t), s) != hipSuccess ||
+      launch_mu_pairs(mk->U, mk->Q, mk->V, mk->P, mk->in_dtype, mk->ld_x, mk->ld_y,
+                      mk->N, mk->M, mk->d, mk->sigma, a, b, xs, ys, count, mu_out,
+                      bad, s) != hipSuccess ||
+      hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = IPFP_EHIP;
+  hipFree(bad);
+  if (rc == IPFP_OK && hb) rc = IPFP_EINVAL;
+  return rc;
+}
+
+int ipfp_pack_side(ipfp_ctx* ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
+                   const void* A, const void* B, int64_t ld, ipfp_dtype compute,
+                   void* out, float* scale_out, int64_t* kpad_out, void* stream) {
+  if (!ctx || !kpad_out || rows < 1 || d < 1 || d > 128 || ld < d) return IPFP_EINVAL;
+  if (compute != IPFP_BF16 && compute != IPFP_FP8E4M3) return IPFP_EINVAL;
+  const int64_t kpad = fused_kpad(d, compute);
+  *kpad_out = kpad;
+  if (!out) return IPFP_OK;
+  if (!A || !B || (compute == IPFP_FP8E4M3 && !scale_out)) return IPFP_EINVAL;
+  if (in_dtype != IPFP_F64 && in_dtype != IPFP_F32 && in_dtype != IPFP_BF16)
+    return IPFP_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IPFP_EHIP;
+  char* mem = nullptr;
+  const size_t bytes = align_up(sizeof(Ctl), 256) + rows * sizeof(float) * 2;
+  HIPCHK(hipMalloc((void**)&mem, bytes));
+  Ctl* ctl = (Ctl*)mem;
+  float* norm = (float*)(mem + align_up(sizeof(Ctl), 256));
+  float* sc = scale_out ? scale_out : norm + rows;
+  Ctl hc{};
+  int rc = IPFP_OK;
+  if (hipMemsetAsync(ctl, 0, sizeof(Ctl), s) != hipSuccess ||
+      launch_pack(A, B, in_dtype, ld, rows, d, compute, kpad, out, sc, norm, ctl, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = IPFP_EHIP;
+  hipFree(mem);
+  if (rc == IPFP_OK && hc.nonfinite) rc = IPFP_ENONFINITE;
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+"""GPU parity of the fused (on-the-fly MFMA) path against the FP64 oracle.
+
+The oracle is fed the same quantised factor values (its own BF16 / e4m3
+rounding), so the comparison isolates kernel error from quantisation error."""
+import numpy as np
+import pytest
+
+import workloads
+from helpers import banner, market_tensors, rel_err, require_gpu, to_dev
+from oracle import closed, ipfp as O, quant
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2411_19214_amd as L
+    return L
+
+
+def quantised(mk, compute):
+    """Oracle-side values of the packed operands, as float64 U,Q,V,P."""
+    if compute == "bf16":
+        return tuple(quant.bf16_round(t).astype(np.float64) for t in (mk.U, mk.Q, mk.V, mk.P))
+    X = np.concatenate([mk.U, mk.Q], 1).astype(np.float64)
+    Y = np.concatenate([mk.V, mk.P], 1).astype(np.float64)
+    Xq, _ = quant.e4m3_quantize_rows(X)
+    Yq, _ = quant.e4m3_quantize_rows(Y)
+    d = mk.d
+    return Xq[:, :d], Xq[:, d:], Yq[:, :d], Yq[:, d:]
+
+
+def oracle_quantised(mk, compute, sweeps, check_every=1, tol=0.0):
+    U, Q, V, P = quantised(mk, compute)
+    K = O.kernel_matrix(O.surplus_from_factors(U, Q, V, P), mk.sigma)
+    return K, O.ipfp_batch(K, mk.n, mk.m, tol=tol, max_sweeps=sweeps, check_every=check_every)
+
+
+@pytest.mark.parametrize("compute", ["bf16", "fp8"])
+def test_pack_side_is_bit_exact(torch, lib, compute):
+    banner(f"pack {compute}")
+    mk = workloads.config_market(2, N=777, M=5)
+    A = np.concatenate([mk.U[:, :5] * 50.0, mk.U[:, 5:] * 1e-3], 1).astype(np.float32)
+    A[0] = 0.0
+    B = mk.Q
+    codes, scale = lib.pack_side(to_dev(torch, A), to_dev(torch, B), compute)
+    X = np.concatenate([A, B], 1)
+    kp = codes.shape[1]
+    if compute == "bf16":
+        want = np.zeros((777, kp), np.uint16)
+        want[:, :64] = quant.bf16_bits(X)
+        assert np.array_equal(codes.cpu().numpy().view(np.uint16), want)
+    else:
+        Xq, s = quant.e4m3_quantize_rows(X.astype(np.float64))
+        want = np.zeros((777, kp), np.uint8)
+        want[:, :64] = quant.e4m3_codes(Xq / s[:, None])
+        assert np.array_equal(scale.cpu().numpy().astype(np.float64), s)
+        assert np.array_equal(codes.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("N,M,d", [(1, 1, 16), (2, 31, 16), (33, 257, 32), (257, 33, 32),
+                                   (1000, 700, 64), (700, 1000, 64), (300, 400, 8),
+                                   (129, 513, 50), (64, 64, 128)])
+def test_fused_bf16_ragged_shapes(torch, lib, N, M, d):
+    banner(f"fused bf16 {N}x{M} d={d}")
+    mk = workloads.factor_market(N, M, d, 1.0 / d, 0.7, "uint1-5", seed=N * 31 + M + d)
+    U, Q, V, P, n, m = market_tensors(torch, mk)
+    a, b, info = lib.solve_market(U, Q, V, P, n, m, mk.sigma, max_sweeps=20, check_every=5)
+    K, r = oracle_quantised(mk, "bf16", 20, check_every=5)
+    assert info.sweeps == 20 and len(info.residuals) == 4
+    assert rel_err(a.cpu().numpy(), r.a) < 2e-5
+    assert rel_err(b.cpu().numpy(), r.b) < 2e-5
+    np.testing.assert_allclose(info.residuals, r.res_hist, rtol=5e-3, atol=1e-9)
+
+
+@pytest.mark.parametrize("N,M,d", [(33, 257, 32), (1000, 700, 64), (500, 300, 128)])
+def test_fused_fp8_ragged_shapes(torch, lib, N, M, d):
+    banner(f"fused fp8 {N}x{M} d={d}")
+    mk = workloads.factor_market(N, M, d, 1.0 / d, 1.0, "uint1-5", seed=N + M + d)
+    U, Q, V, P, n, m = market_tensors(torch, mk)
+    a, b, info = lib.solve_market(U, Q, V, P, n, m, mk.sigma, max_sweeps=20, check_every=5,
+                                  compute="fp8")
+    K, r = oracle_quantised(mk, "fp8", 20, check_every=5)
+    assert rel_err(a.cpu().numpy(), r.a) < 2e-5
+    assert rel_err(b.cpu().numpy(), r.b) < 2e-5
+
+
+def test_fused_c3_distribution_reduced(torch, lib):
+    """C3's distribution (d = 64, sigma = 1, m in 1..10) at 8192 x 6000."""
+    banner("fused C3-shape 8192x6000")
+    mk = workloads.config_market(3, N=8192, M=6000)
+    U, Q, V, P, n, m = market_tensors(torch, mk)
+    a, b, info = lib.solve_market(U, Q, V, P, n, m, mk.sigma, max_sweeps=30, check_every=10)
+    K, r = oracle_quantised(mk, "bf16", 30, check_every=10)
+    assert rel_err(a.cpu().numpy(), r.a) < 2e-5
+    assert rel_err(b.cpu().numpy(), r.b) < 2e-5
+
+
+def test_fused_equals_plain_on_same_surplus(torch, lib):
+    """Sec. 3.3: the mini-batch form makes no approximation. With BF16-exact
+    factors both paths see the same Phi."""
+    banner("fused vs plain")
+    mk = workloads.config_market(2, N=2000, M=1500)
+    for t in (mk.U, mk.Q, mk.V, mk.P):
+        t[...] = quant.bf16_round(t)
+    U, Q, V, P, n, m = market_tensors(torch, mk)
+    af, bf, _ = lib.solve_market(U, Q, V, P, n, m, mk.sigma, max_sweeps=40)
+    ap, bp, _ = lib.solve_market(U, Q, V, P, n, m, mk.sigma, max_sweeps=40, path="plain",
+                                 compute="f64")
+    assert rel_err(af.cpu().numpy(), ap.cpu().numpy()) < 2e-5
+    assert rel_err(bf.cpu().numpy(), bp.cpu().numpy()) < 2e-5
+
+
+def test_fused_deterministic_and_split_independent(torch, lib):
+    banner("fused determinism / splits")
+    mk = workloads.config_market(3, N=3000, M=5000)
+    U, Q, V, P, n, m = market_tensors(torch, mk)
+    runs = [lib.solve_market(U, Q, V, P, n, m, mk.sigma, max_sweeps=15, splits=4)
+            for _ in range(2)]
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    for splits, tr in ((1, 512), (7, 256), (16, 512)):
+        a, b, _ = lib.solve_market(U, Q, V, P, n, m, mk.sigma, max_sweeps=15, splits=splits,
+                                   tile_rows=tr)
+        assert rel_err(a.cpu().numpy(), runs[0][0].cpu().numpy()) < 1e-6
+        assert rel_err(b.cpu().numpy(), runs[0][1].cpu().numpy()) < 1e-6
+
+
+def test_fused_uniform_market_closed_form(torch, lib):
+    """Constant surplus c (BF16-exact): the converged scalings solve the
+    uniform market's quadratic."""
+    banner("fused uniform closed form")
+    N, M, d = 3000, 2000, 8
+    U = np.zeros((N, d), np.float32)
+    V = np.zeros((M, d), np.float32)
+    U[:, 0] = 0.75
+    V[:, 0] = 1.0
+    Z = np.zeros_like(U)
+    W = np.zeros_like(V)
+    mu, u, v = closed.uniform_market(0.75, 1.0, 2.0, N, M, 1.0)
+    a, b, info = lib.solve_market(to_dev(torch, U), to_dev(torch, Z), to_dev(torch, V),
+                                  to_dev(torch, W), to_dev(torch, np.ones(N)),
+                                  to_dev(torch, np.full(M, 2.0)), 1.0, tol=1e-9,
+                                  max_sweeps=3000)
+    assert rel_err(a.cpu().numpy(), np.full(N, u)) < 1e-5
+    assert rel_err(b.cpu().numpy(), np.full(M, v)) < 1e-5
+
+
+def test_fused_separable_replay(torch, lib):
+    """Phi_xy = alpha_x + gamma_y through factors (alpha, 1) . (1, gamma):
+    sweep-by-sweep parity with the O(N + M) replay."""
+    banner("fused separable replay")
+    N, M = 20000, 12000
+    rng = np.random.default_rng(7)
+    al = np.round(rng.uniform(-1, 1, N) * 64) / 64
+    ga = np.round(rng.uniform(-1, 1, M) * 64) / 64
+    U = np.zeros((N, 4), np.float32)
+    V = np.zeros((M, 4), np.float32)
+    U[:, 0], U[:, 1] = al, 1.0
+    V[:, 0], V[:, 1] = 1.0, ga
+    n = np.ones(N)
+    m = rng.integers(1, 6, M).astype(np.float64)
+    r = closed.separable_replay(al, ga, n, m, 0.5, max_sweeps=25, check_every=5)
+    a, b, info = lib.solve_market(to_dev(torch, U), to_dev(torch, np.zeros_like(U)),
+                                  to_dev(torch, V), to_dev(torch, np.zeros_like(V)),
+                                  to_dev(torch, n), to_dev(torch, m), 0.5, max_sweeps=25,
+                                  check_every=5)
+    assert rel_err(a.cpu().numpy(), r.a) < 2e-5
+    assert rel_err(b.cpu().numpy(), r.b) < 2e-5
+
+
+def test_fused_exact_shift_fallback(torch, lib):
+    """Orthogonal factors of large norm: the Cauchy-Schwarz first shift is
+    ~300 binades too low, every first-pass sum underflows and the exact-shift
+    fallback must recompute those rows."""
+    banner("fused fixup")
+    N, M, d = 300, 200, 8
+    mk = workloads.factor_market(N, M, d, 1.0 / d, 1.0, "unit", seed=11)
+    mk.U[:, 0] = 20.0
+    mk.V[:, 1] = 20.0
+    mk.U[:, 1] = 0.0
+    mk.V[:, 0] = 0.0
+    U, Q, V, P, n, m = market_tensors(torch, mk)
+    a, b, info = lib.solve_market(U, Q, V, P, n, m, mk.sigma, max_sweeps=10)
+    assert info.fixups > 0
+    K, r = oracle_quantised(mk, "bf16", 10)
+    assert rel_err(a.cpu().numpy(), r.a) < 2e-5
+    assert rel_err(b.cpu().numpy(), r.b) < 2e-5
+
+
+def test_fused_graph_and_resident_market(torch, lib):
+    banner("fused graph / resident")
+    mk = workloads.config_market(2, N=1500, M=1200)
+    U, Q, V, P, n, m = market_tensors(torch, mk)
+    a0, b0, i0 = lib.solve_market(U, Q, V, P, n, m, mk.sigma, tol=1e-7, max_sweeps=400,
+                                  check_every=4)
+    a1, b1, i1 = lib.solve_market(U, Q, V, P, n, m, mk.sigma, tol=1e-7, max_sweeps=400,
+                                  check_every=4, use_graph=True)
+    assert torch.equal(a0, a1) and torch.equal(b0, b1) and i0.sweeps == i1.sweeps
+    with lib.Market(U, Q, V, P, n, m, mk.sigma, tol=1e-7, max_sweeps=400,
+                    check_every=4) as h:
+        while not h.run(3):
+            pass
+        a2, b2, i2 = h.read()
+    assert torch.equal(a0, a2) and torch.equal(b0, b2) and i2.sweeps == i0.sweeps
+
+
+def test_mu_pairs(torch, lib):
+    banner("mu pairs")
+    mk = workloads.config_market(1, N=50, M=40)
+    U, Q, V, P, n, m = market_tensors(torch, mk, torch.float64)
+    a, b, _ = lib.solve_market(U, Q, V, P, n, m, mk.sigma, max_sweeps=30, path="plain",
+                               compute="f64")
+    xs = torch.arange(50).repeat_interleave(40)
+    ys = torch.arange(40).repeat(50)
+    mu = lib.mu_pairs(U, Q, V, P, mk.sigma, a, b, xs, ys).cpu().numpy().reshape(50, 40)
+    K = O.kernel_matrix(O.surplus_from_factors(mk.U, mk.Q, mk.V, mk.P), mk.sigma)
+    want = O.matching(K, a.cpu().numpy(), b.cpu().numpy())
+    assert rel_err(mu, want) < 1e-13
+    with pytest.raises(lib.IPFPError):
+        lib.mu_pairs(U, Q, V, P, mk.sigma, a, b, torch.tensor([50]), torch.tensor([0]))
