@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Throughput of the IPFP sweep on one MI355X, in pair-evaluations per second.
+
+A step is one IPFP sweep over the whole market (both half-sweeps: the row pass
+s = K v / 2 with the quadratic update of u, then the column pass with the new
+u, plus the residual of the previous state), so one step evaluates every
+kernel entry twice: pair-evals = 2 N M per sweep.
+
+Default workload: the fused BF16 path on the N = M = 1,000,000, d = 64
+market (factors N(0, 1/64), sigma = 1, n = 1, m uniform on 1..10), with the
+factors resident in HBM before timing starts. The same JSON line also reports
+the plain FP32 (materialised K) and fused BF16 paths on the 20,000 x 20,000,
+d = 32 market at a fixed 500 sweeps, the roofline of the dominant kernel and
+the CPU oracle timed on a bounded sample of the default workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+METRIC = ("IPFP pair-evals/s, fused BF16 vs plain FP32 @ stated margin err; "
+          "p99 solve ms")
+PEAK_BF16_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
+PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def factor_tensors(torch, mk):
+    dev = torch.device("cuda", 0)
+    return tuple(torch.from_numpy(t).to(dev) for t in (mk.U, mk.Q, mk.V, mk.P, mk.n, mk.m))
+
+
+def run_fused(torch, L, mk, steps, warmup, compute="bf16"):
+    """Resident market: warm up, then time exactly `steps` sweeps."""
+    U, Q, V, P, n, m = factor_tensors(torch, mk)
+    h = L.Market(U, Q, V, P, n, m, mk.sigma, tol=0.0, max_sweeps=warmup + steps + 1,
+                 check_every=1, compute=compute, time_passes=True)
+    if warmup:
+        h.run(warmup)
+    _, _, before = h.read()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    h.run(steps)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    _, _, after = h.read()
+    h.run(1)                       # final residual of the last state (untimed)
+    _, _, fin = h.read()
+    h.close()
+    launches = after.pass_launches - before.pass_launches
+    pass_ms = after.pass_ms - before.pass_ms
+    return dict(ms=ms, pass_ms=pass_ms, launches=launches, final_res=fin.final_res,
+                setup_ms=before.setup_ms, fixups=fin.fixups, sweeps=fin.sweeps)
+
+
+def run_c2(torch, L, sweeps=500):
+    """Plain FP32 vs fused BF16 on the same 20k x 20k market, fixed sweeps."""
+    mk = workloads.config_market(2)
+    U, Q, V, P, n, m = factor_tensors(torch, mk)
+    out = {}
+    for path, compute in (("plain", "f32"), ("fused", "bf16")):
+        kw = dict(path=path, compute=compute, tol=0.0, max_sweeps=sweeps, check_every=50,
+                  use_graph=path == "fused")
+        L.solve_market(U, Q, V, P, n, m, mk.sigma, **dict(kw, max_sweeps=5))  # warm
+        torch.cuda.synchronize()
+        a, b, info = L.solve_market(U, Q, V, P, n, m, mk.sigma, **kw)
+        torch.cuda.synchronize()
+        loop_s = info.loop_ms / 1e3
+        # loop_ms covers sweeps + 1 row passes (final residual)
+        pe = 2.0 * mk.N * mk.M * sweeps / loop_s
+        out[f"{path}_{compute}"] = dict(pair_evals_per_s=pe, sweeps=info.sweeps,
+                                        loop_ms=info.loop_ms, setup_ms=info.setup_ms,
+                                        final_res=info.final_res)
+        # time to tol 1e-6 (the configuration's tolerance)
+        a, b, info = L.solve_market(U, Q, V, P, n, m, mk.sigma,
+                                    **dict(kw, tol=1e-6, check_every=1))
+        out[f"{path}_{compute}"]["sweeps_to_1e-6"] = info.sweeps
+        out[f"{path}_{compute}"]["ms_to_1e-6"] = info.loop_ms
+    p, f = out["plain_f32"], out["fused_bf16"]
+    out["fused_over_plain"] = f["pair_evals_per_s"] / p["pair_evals_per_s"]
+    return out
+
+
+def cpu_baseline(mk, budget_s=15.0):
+    """The oracle's mini-batch half-step (FP64 GEMM + exp + matvec) on row
+    blocks of the default workload, timed on the host until ~budget_s."""
+    from oracle import ipfp as O
+    X = np.concatenate([mk.U, mk.Q], 1).astype(np.float64)
+    Y = np.concatenate([mk.V, mk.P], 1).astype(np.float64)
+    v = np.ones(mk.M)
+    B = 64
+    rows = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and rows < mk.N:
+        O.half_step_rows(X[rows:rows + B], Y, v, mk.sigma)
+        rows += B
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": rows * mk.M / dt, "unit": "pair-evals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{rows} rows x {mk.M} columns of one row half-step (mini-batch "
+                      f"blocks of {B} rows: FP64 surplus GEMM, exp, matvec), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--size", type=int, default=1_000_000,
+                    help="N = M of the default workload (1e6 unless testing)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has "
+              "no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2411_19214_amd as L
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    L.library()
+    cfg = workloads.CONFIGS[3]
+    log(f"generating C3 market N=M={args.size} d={cfg['d']}")
+    mk = workloads.config_market(3, N=args.size, M=args.size)
+    log("timing fused BF16")
+    r = run_fused(torch, L, mk, args.steps, args.warmup)
+    N, M, d = mk.N, mk.M, mk.d
+    value = 2.0 * N * M * args.steps / (r["ms"] / 1e3)
+    avg_launch_s = r["pass_ms"] / r["launches"] / 1e3
+    flops_per_launch = 4.0 * d * N * M        # 2 flops x 2d contraction per pair
+    achieved_tflops = flops_per_launch / avg_launch_s / 1e12
+    exp_rate = N * M / avg_launch_s
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"fused BF16 IPFP sweep, N=M={N}, d={d} per side "
+                               f"(Phi=[U|Q][V|P]^T, K=2d={2 * d}), sigma=1, n=1, m~U{{1..10}}",
+                   "N": N, "M": M, "d": d, "sigma": mk.sigma, "path": "fused",
+                   "compute": "bf16 MFMA, fp32 accumulate/exp2, fp64 sums+updates"},
+        "final_res": r["final_res"],
+        "sweeps_done": r["sweeps"],
+        "fixups": r["fixups"],
+        "pack_ms": r["setup_ms"],
+        "roofline": {"bound": "mfma", "achieved": achieved_tflops,
+                     "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / PEAK_BF16_TFLOPS, "traffic": None,
+                     "kernel": "k_fused_pass", "launch_ms": avg_launch_s * 1e3,
+                     "flops_per_launch": flops_per_launch,
+                     "exp2_per_s": exp_rate},
+    }
+    if not args.no_c2:
+        log("C2: plain FP32 vs fused BF16, 500 sweeps")
+        line["c2_20k"] = run_c2(torch, L)
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(mk)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -207,19 +207,25 @@ static SweepParams sweep_params(const ipfp_handle* h) {
   return sp;
 }
 
-static hipError_t timed(ipfp_handle* h, bool timing, hipStream_t s,
-                        hipError_t (*fn)(const FusedPass&, Ctl*, hipStream_t),
-                        const FusedPass& fp) {
-  if (!timing) return fn(fp, h->ctl, s);
-  hipEvent_t a, b;
-  hipEventCreate(&a);
-  hipEventCreate(&b);
-  hipEventRecord(a, s);
-  hipError_t e = fn(fp, h->ctl, s);
-  hipEventRecord(b, s);
+// Runs `fn` (one kernel launch on `s`), bracketed by HIP events when timing;
+// the event pairs are summed after the next synchronisation.
+template <typename F>
+static hipError_t timed(ipfp_handle* h, bool timing, hipStream_t s, F&& fn) {
+  if (!timing) return fn();
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipEventRecord(a, s);
+  if (e == hipSuccess) e = fn();
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    return e;
+  }
   h->evs.push_back(a);
   h->evs.push_back(b);
-  return e;
+  return hipSuccess;
 }
 
 // One sweep unit: the row half-sweep for the current state, the convergence
@@ -227,40 +233,21 @@ static hipError_t timed(ipfp_handle* h, bool timing, hipStream_t s,
 static hipError_t enqueue_unit(ipfp_handle* h, hipStream_t s, bool timing) {
   hipError_t e;
   const SweepParams sp = sweep_params(h);
+  int nb = 0;
   if (h->plain) {
-    int nb = 0;
-    hipEvent_t a = nullptr, b = nullptr;
-    if (timing) {
-      hipEventCreate(&a);
-      hipEventCreate(&b);
-      hipEventRecord(a, s);
-    }
-    e = launch_plain_row(h->K, h->kdt, h->ldk, h->N, h->M, h->cshift, h->v,
-                         h->mk.n, h->u2, h->ut, h->res_block, &nb, h->ctl, s);
-    if (timing) {
-      hipEventRecord(b, s);
-      h->evs.push_back(a);
-      h->evs.push_back(b);
-    }
+    e = timed(h, timing, s, [&] {
+      return launch_plain_row(h->K, h->kdt, h->ldk, h->N, h->M, h->cshift, h->v, h->mk.n,
+                              h->u2, h->ut, h->res_block, &nb, h->ctl, s);
+    });
     if (e != hipSuccess) return e;
     e = launch_check(h->ctl, h->res_block, nb, h->hist, sp, s);
     if (e != hipSuccess) return e;
-    if (timing) {
-      hipEventCreate(&a);
-      hipEventCreate(&b);
-      hipEventRecord(a, s);
-    }
-    e = launch_plain_col(h->K, h->kdt, h->ldk, h->N, h->M, h->ut, h->psplits,
-                         h->part, h->mk.m, h->v, h->ctl, s);
-    if (timing) {
-      hipEventRecord(b, s);
-      h->evs.push_back(a);
-      h->evs.push_back(b);
-    }
-    return e;
+    return timed(h, timing, s, [&] {
+      return launch_plain_col(h->K, h->kdt, h->ldk, h->N, h->M, h->ut, h->psplits, h->part,
+                              h->mk.m, h->v, h->ctl, s);
+    });
   }
-  int nb = 0;
-  e = timed(h, timing, s, launch_fused_pass, h->rowp);
+  e = timed(h, timing, s, [&] { return launch_fused_pass(h->rowp, h->ctl, s); });
   if (e != hipSuccess) return e;
   e = launch_fused_combine(h->rowp, h->u2, 1, h->ctl, &nb, s);
   if (e != hipSuccess) return e;
@@ -269,7 +256,7 @@ static hipError_t enqueue_unit(ipfp_handle* h, hipStream_t s, bool timing) {
   if (e != hipSuccess) return e;
   e = launch_check(h->ctl, h->res_block, h->nres_row, h->hist, sp, s);
   if (e != hipSuccess) return e;
-  e = timed(h, timing, s, launch_fused_pass, h->colp);
+  e = timed(h, timing, s, [&] { return launch_fused_pass(h->colp, h->ctl, s); });
   if (e != hipSuccess) return e;
   e = launch_fused_combine(h->colp, h->v, 0, h->ctl, &nb, s);
   if (e != hipSuccess) return e;
@@ -290,8 +277,8 @@ static void collect_events(ipfp_handle* h) {
       h->pass_ms += ms;
       h->pass_launches += 1;
     }
-    hipEventDestroy(h->evs[k]);
-    hipEventDestroy(h->evs[k + 1]);
+    (void)hipEventDestroy(h->evs[k]);
+    (void)hipEventDestroy(h->evs[k + 1]);
   }
   h->evs.clear();
 }
@@ -379,10 +366,10 @@ static void release(ipfp_ctx* ctx, size_t bytes) {
 static void destroy_handle(ipfp_handle* h) {
   if (!h) return;
   collect_events(h);
-  if (h->graph) hipGraphExecDestroy(h->graph);
-  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
-  if (h->host_ctl) hipHostFree(h->host_ctl);
-  if (h->mem) hipFree(h->mem);
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->host_ctl) (void)hipHostFree(h->host_ctl);
+  if (h->mem) (void)hipFree(h->mem);
   if (h->ctx && h->bytes) release(h->ctx, h->bytes);
   delete h;
 }
@@ -509,13 +496,13 @@ static int run_impl(ipfp_handle* h, int32_t sweeps, int* done, hipStream_t s) {
       HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < G; ++k) {
         if (enqueue_unit(h, h->cap_stream, false) != hipSuccess) {
-          hipStreamEndCapture(h->cap_stream, &g);
+          (void)hipStreamEndCapture(h->cap_stream, &g);
           return IPFP_EHIP;
         }
       }
       HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
       HIPCHK(hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0));
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       h->graph_units = G;
     }
     while (h->graph && todo >= h->graph_units) {
@@ -532,8 +519,8 @@ static int run_impl(ipfp_handle* h, int32_t sweeps, int* done, hipStream_t s) {
   int rc = read_ctl(h, s);
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) h->loop_ms += ms;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   collect_events(h);
   if (rc != IPFP_OK) return rc;
   if (done) *done = h->host_ctl->done || h->units >= total;
@@ -651,7 +638,7 @@ int ipfp_mu_pairs(ipfp_ctx* ctx, const ipfp_market* mk, const double* a,
       hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     rc = IPFP_EHIP;
-  hipFree(bad);
+  (void)hipFree(bad);
   if (rc == IPFP_OK && hb) rc = IPFP_EINVAL;
   return rc;
 }
@@ -683,7 +670,7 @@ int ipfp_pack_side(ipfp_ctx* ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
       hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     rc = IPFP_EHIP;
-  hipFree(mem);
+  (void)hipFree(mem);
   if (rc == IPFP_OK && hc.nonfinite) rc = IPFP_ENONFINITE;
   return rc;
 }

@@ -75,7 +75,10 @@ def test_fused_bf16_ragged_shapes(torch, lib, N, M, d):
     assert info.sweeps == 20 and len(info.residuals) == 4
     assert rel_err(a.cpu().numpy(), r.a) < 2e-5
     assert rel_err(b.cpu().numpy(), r.b) < 2e-5
-    np.testing.assert_allclose(info.residuals, r.res_hist, rtol=5e-3, atol=1e-9)
+    # the GPU residual is formed from FP32 exp2 terms: each term carries ~2
+    # FP32 ulps of relative error, so the residual has an absolute floor of
+    # about 2.4e-7 below which it cannot follow the FP64 oracle
+    np.testing.assert_allclose(info.residuals, r.res_hist, rtol=5e-3, atol=3e-7)
 
 
 @pytest.mark.parametrize("N,M,d", [(33, 257, 32), (1000, 700, 64), (500, 300, 128)])
