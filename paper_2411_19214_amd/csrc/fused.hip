@@ -170,7 +170,16 @@ struct Op<true> {  // FP8 e4m3, v_mfma_scale_f32_32x32x64_f8f6f4
   static constexpr int ES = 1, SB = 32, KS = 64;
 };
 
-constexpr int kTY = 64;  // reduced rows staged per LDS buffer (two 32-row subtiles)
+// Reduced rows staged per LDS buffer (a multiple of 32) and whether the
+// epilogue is explicitly interleaved with the next accumulator's MFMAs; both
+// are build-time tuning knobs.
+#ifndef IPFP_TY
+#define IPFP_TY 64
+#endif
+#ifndef IPFP_SCHED
+#define IPFP_SCHED 1
+#endif
+constexpr int kTY = IPFP_TY;
 
 template <int KP, int XT, int WAVES, bool FP8>
 __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
@@ -243,36 +252,61 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
   float pb = 0.f;
   int psc = 127;
   auto gload = [&](int tile) {
+    // Branch-free, so that a whole tile is one scheduling region: rows past
+    // the end are clamped to the last row (a valid read) and masked by a -inf
+    // bias; surplus threads repeat the last chunk, and every thread loads the
+    // bias of row tid % kTY (duplicates store identical values).
     const int64_t y0 = (int64_t)tile * kTY;
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
-      const int chunk = tid + q * NT;
+      const int chunk = min(tid + q * NT, CH - 1);
       const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
-      const int64_t y = y0 + r;
-      intx4 v = {0, 0, 0, 0};
-      if (chunk < CH && y < L) v = *reinterpret_cast<const intx4*>(Yr + y * RB + cb * 16);
-      pre[q] = v;
+      const int64_t y = min(y0 + r, (int64_t)L - 1);
+      pre[q] = *reinterpret_cast<const intx4*>(Yr + y * RB + cb * 16);
     }
-    if (tid < kTY) {
-      const int64_t y = y0 + tid;
-      pb = y < L ? bias[y] : -INFINITY;
-      if (FP8) psc = y < L ? (int)((__float_as_uint(yscale[y]) >> 23) & 0xFF) : 127;
-    }
+    const int64_t y = y0 + (tid % kTY);
+    const int64_t yc = min(y, (int64_t)L - 1);
+    const float bb = bias[yc];
+    pb = y < L ? bb : -INFINITY;
+    if (FP8) psc = (int)((__float_as_uint(yscale[yc]) >> 23) & 0xFF);
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
-      const int chunk = tid + q * NT;
-      if (chunk < CH) {
-        const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
-        *reinterpret_cast<intx4*>(&ys[buf][r * LS + cb * 16]) = pre[q];
-      }
+      const int chunk = min(tid + q * NT, CH - 1);
+      const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
+      *reinterpret_cast<intx4*>(&ys[buf][r * LS + cb * 16]) = pre[q];
     }
-    if (tid < kTY) {
-      bs[buf][tid] = pb;
-      if (FP8) ysc[buf][tid] = psc;
-    }
+    bs[buf][tid % kTY] = pb;
+    if (FP8) ysc[buf][tid % kTY] = psc;
   };
+
+  // The epilogue (exp2 and sums) of each 32x32 accumulator runs while the
+  // matrix cores compute the next one: `accp` holds the accumulator whose
+  // epilogue is pending, `bvp` its biases; its output tile is always the one
+  // computed just before the current one, so its running-sum index is static.
+  // The first pending epilogue is a dummy with -inf biases (adds zero).
+  floatx16 accp;
+  float bvp[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    accp[r] = 0.f;
+    bvp[r] = -INFINITY;
+  }
+  auto epilogue = [&](const floatx16& a, const float* b, double& acc_run) {
+    float e[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) e[r] = __builtin_amdgcn_exp2f(fmaf(a[r], c, b[r]));
+#pragma unroll
+    for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+      for (int r = 0; r < w; ++r) e[r] += e[r + w];
+    acc_run += (double)e[0];
+  };
+  // VALU instructions of one epilogue (16 fma, 16 exp, 15 add, cvt, add_f64)
+  // spread over the NS matrix instructions of the next accumulator
+  constexpr int kEpiValu = 49;
+  constexpr int kValuPerMfma = (kEpiValu + NS - 1) / NS;
 
   if (t0 < t1) {
     gload(t0);
@@ -282,7 +316,7 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
 
   for (int tile = t0; tile < t1; ++tile) {
     const int buf = (tile - t0) & 1;
-    if (tile + 1 < t1) gload(tile + 1);
+    gload(min(tile + 1, t1 - 1));   // prefetch (the last iteration reloads harmlessly)
 #pragma unroll
     for (int sub = 0; sub < SUB; ++sub) {
       const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
@@ -325,19 +359,23 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afrag[s], bfrag[t][s], acc, 0, 0, 0);
           }
         }
-        float e[16];
+        epilogue(accp, bvp, run[t == 0 ? XT - 1 : t - 1]);
+#if IPFP_SCHED
 #pragma unroll
-        for (int r = 0; r < 16; ++r) e[r] = __builtin_amdgcn_exp2f(fmaf(acc[r], c, bv[r]));
+        for (int s = 0; s < NS; ++s) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);             // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x002, kValuPerMfma, 0);  // VALU
+        }
+#endif
+        accp = acc;
 #pragma unroll
-        for (int w = 8; w > 0; w >>= 1)
-#pragma unroll
-          for (int r = 0; r < w; ++r) e[r] += e[r + w];
-        run[t] += (double)e[0];
+        for (int r = 0; r < 16; ++r) bvp[r] = bv[r];
       }
     }
-    if (tile + 1 < t1) lstore(buf ^ 1);
+    lstore(buf ^ 1);
     __syncthreads();
   }
+  epilogue(accp, bvp, run[XT - 1]);
 
 #pragma unroll
   for (int t = 0; t < XT; ++t) {
