@@ -198,15 +198,19 @@ int ipfp_mu_pairs(ipfp_ctx *ctx, const ipfp_market *mk, const double *a,
                   const double *b, const int64_t *xs, const int64_t *ys,
                   int64_t count, double *mu_out, void *stream);
 
-/* The fused path's packed operand of one side: rows [U|Q] (or [V|P])
- * concatenated, zero-padded to `kpad` columns and rounded to `compute`
- * (BF16: 2-byte codes; FP8E4M3: 1-byte codes plus one FP32 power-of-two
- * scale per row written to `scale_out`). `out` is a device buffer of
- * rows * kpad codes; kpad is returned through *kpad_out (pass out = NULL to
- * query it). Used to check the packing bit for bit. */
+/* The fused path's packed operand of one side (Sec. 3.3's factor matrices as
+ * the matrix cores read them): rows p [A|B] concatenated, zero-padded to
+ * `kpad` columns and rounded to `compute`, where p = sqrt(log2(e)/(2 sigma))
+ * rounded to FP32 (p = 1 when sigma = 0), applied in FP32 after rounding the
+ * input to FP32. BF16: 2-byte codes of the round-to-nearest-even value.
+ * FP8E4M3: 1-byte e4m3fn codes of p x / s, with one FP32 power-of-two scale
+ * s per row (the smallest with max |p x| <= 448 s) written to `scale_out`.
+ * `out` is a device buffer of rows * kpad codes; kpad is returned through
+ * *kpad_out (pass out = NULL to query it). The solver packs with the market's
+ * sigma, so this reproduces its operands bit for bit. */
 int ipfp_pack_side(ipfp_ctx *ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
                    const void *A, const void *B, int64_t ld, ipfp_dtype compute,
-                   void *out, float *scale_out, int64_t *kpad_out,
+                   double sigma, void *out, float *scale_out, int64_t *kpad_out,
                    void *stream);
 
 #ifdef __cplusplus

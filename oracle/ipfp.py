@@ -67,6 +67,15 @@ def kernel_matrix(Phi, sigma: float) -> np.ndarray:
     return np.exp(t)
 
 
+def kernel_from_log2(T) -> np.ndarray:
+    """K = 2^T for a surplus given in log2 units, T = Phi log2(e) / (2 sigma)
+    (the same matrix as ``kernel_matrix``; 2^T = exp(Phi / 2 sigma))."""
+    T = np.asarray(T, dtype=np.float64)
+    if T.size and np.max(np.abs(T)) >= 1000.0:
+        raise OverflowError("2^T leaves FP64 range")
+    return np.exp2(T)
+
+
 def root(marg, s):
     """Positive root w of w^2 + 2 s w - marg = 0, i.e. sqrt(marg + s^2) - s
     (eq. 6), evaluated as marg / (s + sqrt(s^2 + marg)). For s beyond 1e150 the

@@ -18,8 +18,15 @@ quantised values, produced here independently of the GPU's packing code.
   (its runs use the framework's default precision); this scale rule is a
   reading of this implementation.
 
+* Prescale: the fused GPU path multiplies both sides' factors by
+  p = sqrt(log2(e) / (2 sigma)) (rounded to FP32, applied in FP32) before
+  rounding, so that the product of the two packed operands is the surplus in
+  log2 units, T = Phi log2(e) / (2 sigma), and K = 2^T. ``packed_rows``
+  reproduces those operand values; with them the oracle computes K = 2^T.
+
 Parity status: pinned in the test suite against brute-force nearest-value
-search over every BF16 / e4m3 code.
+search over every BF16 / e4m3 code; ``packed_rows`` against the GPU packing
+bit for bit and, with p = 1, against the plain rounding functions.
 """
 from __future__ import annotations
 
@@ -107,3 +114,23 @@ def e4m3_quantize_rows(rows):
     rows = np.asarray(rows, dtype=np.float64)
     s = pow2_row_scale(rows)
     return e4m3_round(rows / s[:, None]) * s[:, None], s
+
+
+LOG2_E = 1.4426950408889634
+
+
+def prescale(sigma: float) -> np.float32:
+    """p = sqrt(log2(e) / (2 sigma)) rounded to FP32 (1 for sigma = 0)."""
+    if sigma <= 0:
+        return np.float32(1.0)
+    return np.float32(np.sqrt(np.float64(LOG2_E) / (2.0 * float(sigma))))
+
+
+def packed_rows(rows, sigma: float, compute: str) -> np.ndarray:
+    """FP64 values of the fused path's operand rows p [A|B] ("bf16" or "fp8"):
+    the input is rounded to FP32, multiplied by p in FP32, then rounded."""
+    x = np.asarray(rows, dtype=np.float32) * prescale(sigma)
+    if compute == "bf16":
+        return bf16_round(x).astype(np.float64)
+    q, _ = e4m3_quantize_rows(x.astype(np.float64))
+    return q

@@ -85,9 +85,12 @@ class Context:
         self.device = device
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib._LIB is not None:
-            _lib._LIB.ipfp_destroy(self.handle)
-            self.handle = None
+        try:
+            if getattr(self, "handle", None) and _lib._LIB is not None:
+                _lib._LIB.ipfp_destroy(self.handle)
+                self.handle = None
+        except Exception:  # interpreter shutdown
+            pass
 
     @classmethod
     def default(cls, device: int = 0) -> "Context":
@@ -275,8 +278,10 @@ class Market:
             self.handle = None
 
     def __del__(self):
-        if _lib._LIB is not None:
+        try:
             self.close()
+        except Exception:  # interpreter shutdown
+            pass
 
     def __enter__(self):
         return self
@@ -301,16 +306,19 @@ def mu_pairs(U, Q, V, P, sigma, a, b, xs, ys, stream=None, ctx=None):
     return out
 
 
-def pack_side(A, B, compute="bf16", stream=None, ctx=None):
-    """The fused path's packed operand of one side: (codes, scales or None).
-    BF16 codes come back as int16 (bit patterns), FP8 codes as uint8."""
+def pack_side(A, B, compute="bf16", sigma=0.0, stream=None, ctx=None):
+    """The fused path's packed operand of one side: (codes, scales or None),
+    prescaled by sqrt(log2(e) / (2 sigma)) as the solver does (no prescale for
+    sigma = 0). BF16 codes come back as int16 (bit patterns), FP8 codes as
+    uint8."""
     torch = _torch()
     rows, d = A.shape
     kpad = ctypes.c_int64()
     ctx = ctx or Context.default(A.device.index or 0)
     lib = library()
     _check(lib.ipfp_pack_side(ctx.handle, rows, d, _dtype_code(A), None, None, A.stride(0),
-                              _DT[compute], None, None, ctypes.byref(kpad), None),
+                              _DT[compute], float(sigma), None, None, ctypes.byref(kpad),
+                              None),
            "ipfp_pack_side")
     if compute == "bf16":
         out = torch.empty((rows, kpad.value), dtype=torch.int16, device=A.device)
@@ -319,7 +327,7 @@ def pack_side(A, B, compute="bf16", stream=None, ctx=None):
         out = torch.empty((rows, kpad.value), dtype=torch.uint8, device=A.device)
         scale = torch.empty(rows, dtype=torch.float32, device=A.device)
     _check(lib.ipfp_pack_side(ctx.handle, rows, d, _dtype_code(A), A.data_ptr(), B.data_ptr(),
-                              A.stride(0), _DT[compute], out.data_ptr(),
+                              A.stride(0), _DT[compute], float(sigma), out.data_ptr(),
                               scale.data_ptr() if scale is not None else None,
                               ctypes.byref(kpad), _stream_ptr(stream)), "ipfp_pack_side")
     return out, scale

@@ -21,6 +21,7 @@ struct Ctl {
   int32_t bad_margin;   // 1 if a margin was not > 0 and finite
   int32_t fix_rows;     // rows queued for the exact-shift fallback (this pass)
   int32_t fix_total;    // rows recomputed by the fallback over the solve
+  int32_t wexp[2];      // fused path: largest binary exponent of u (0), v (1)
   double last_res;      // most recent recorded residual
 };
 
@@ -102,15 +103,15 @@ int plain_splits(int64_t N, int64_t M, ipfp_dtype kdt);
 
 // fused path (fused.hip)
 struct FusedSide {
-  const void* ops;      // packed operand rows (R x kpad codes)
+  const void* ops;      // packed operand rows (rows x kpad codes)
   const float* scale;   // FP8: per-row power-of-two scale, else null
-  const float* norm;    // per-row 2-norm of the packed row (FP32)
   int64_t rows;
 };
 int64_t fused_kpad(int64_t d, ipfp_dtype compute);
+float fused_prescale(double sigma);
 hipError_t launch_pack(const void* A, const void* B, ipfp_dtype in_dt,
                        int64_t ld, int64_t rows, int64_t d, ipfp_dtype compute,
-                       int64_t kpad, void* out, float* scale, float* norm,
+                       int64_t kpad, float prescale, void* out, float* scale,
                        Ctl* ctl, hipStream_t s);
 
 struct FusedPass {
@@ -118,11 +119,12 @@ struct FusedPass {
                             // reduced side (summed over)
   ipfp_dtype compute;
   int64_t kpad;
-  float c;                  // log2(e) / (2 sigma)
-  const float* bias;        // red.rows: log2 of the reduced side's scaling
-  float* shift;             // out.rows: additive shift of the surplus
+  const double* w_red;      // reduced side's scaling (FP64); for a double-
+                            // buffered side the base of both halves
+  int red_dbuf;             // 1: w_red holds two halves, pick by sweep parity
+  int exp_red, exp_out;     // Ctl::wexp indices of the two sides
+  float* shift;             // out.rows: -max_r T_or (log2 units), fixed
   const double* marg;       // out.rows margins
-  float* lw_new;            // out.rows: log2 of the updated scaling
   double* part;             // splits x out.rows partial sums
   double* res_block;        // per-combine-block residual maxima
   int32_t* fix_list;        // out.rows
@@ -131,15 +133,12 @@ struct FusedPass {
   bool residual;            // compute the row residual of the old scaling
 };
 hipError_t launch_fused_pass(const FusedPass& fp, Ctl* ctl, hipStream_t s);
+hipError_t launch_fused_shift(const FusedPass& fp, Ctl* ctl, hipStream_t s);
 hipError_t launch_fused_combine(const FusedPass& fp, double* w2, int dbuf,
                                 Ctl* ctl, int* nblocks, hipStream_t s);
 hipError_t launch_fused_fixup(const FusedPass& fp, double* w2, int dbuf,
                               double* res_slot, Ctl* ctl, hipStream_t s);
-hipError_t launch_initial_shift(const FusedSide& out, const FusedSide& red,
-                                float c, double lscale, const double* wmax_src,
-                                int64_t wmax_len, float* shift, float* tmp,
-                                hipStream_t s);
-hipError_t launch_log2_vec(const double* w, float* lw, int64_t len,
+hipError_t launch_init_exp(const double* w, int64_t len, Ctl* ctl, int idx,
                            hipStream_t s);
 int fused_auto_splits(int64_t R, int64_t L, int rows_per_wg);
 int fused_rows_per_wg(int64_t kpad, ipfp_dtype compute, int tile_rows);

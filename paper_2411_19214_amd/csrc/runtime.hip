@@ -91,11 +91,10 @@ struct ipfp_handle {
   // fused path
   int64_t kpad = 0;
   void *xop = nullptr, *yop = nullptr;
-  float *xscale = nullptr, *yscale = nullptr, *xnorm = nullptr, *ynorm = nullptr;
-  float *xshift = nullptr, *yshift = nullptr, *lu = nullptr, *lv = nullptr;
+  float *xscale = nullptr, *yscale = nullptr;
+  float *xshift = nullptr, *yshift = nullptr;
   double *xpart = nullptr, *ypart = nullptr;
   int32_t *xfix = nullptr, *yfix = nullptr;
-  float* tmp = nullptr;
   FusedPass rowp{}, colp{};
   int row_combine_blocks = 0, col_combine_blocks = 0;
   // loop state
@@ -109,7 +108,6 @@ struct ipfp_handle {
   int pass_launches = 0;
   double loop_ms = 0.0;
   double setup_ms = 0.0;
-  float sigma_c = 0.f;
 };
 
 // ---- sizes -------------------------------------------------------------------
@@ -139,12 +137,8 @@ static void layout(ipfp_handle* h, Carver& cv) {
     h->yop = cv.take<char>((size_t)M * h->kpad * es);
     h->xscale = cv.take<float>(N);
     h->yscale = cv.take<float>(M);
-    h->xnorm = cv.take<float>(N);
-    h->ynorm = cv.take<float>(M);
     h->xshift = cv.take<float>(N);
     h->yshift = cv.take<float>(M);
-    h->lu = cv.take<float>(N);
-    h->lv = cv.take<float>(M);
     const int tr = h->opt.tile_rows > 0 ? h->opt.tile_rows : 512;
     const int rx = fused_rows_per_wg(h->kpad, cd, tr);
     int sx = h->opt.splits > 0 ? h->opt.splits : fused_auto_splits(N, M, rx);
@@ -153,7 +147,6 @@ static void layout(ipfp_handle* h, Carver& cv) {
     h->ypart = cv.take<double>((size_t)sy * M);
     h->xfix = cv.take<int32_t>(N);
     h->yfix = cv.take<int32_t>(M);
-    h->tmp = cv.take<float>(4);
     h->row_combine_blocks = (int)((N + 255) / 256);
     h->col_combine_blocks = (int)((M + 255) / 256);
     h->nres_row = h->row_combine_blocks + fused_fixup_blocks();
@@ -437,30 +430,30 @@ static int open_impl(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* o
     if (e != hipSuccess) return fail(IPFP_EHIP);
   } else {
     const ipfp_dtype cd = opt->compute;
-    const float c = (float)(1.4426950408889634 / (2.0 * mk->sigma));
-    h->sigma_c = c;
-    if (launch_pack(mk->U, mk->Q, mk->in_dtype, mk->ld_x, h->N, mk->d, cd, h->kpad,
-                    h->xop, h->xscale, h->xnorm, h->ctl, s) != hipSuccess ||
-        launch_pack(mk->V, mk->P, mk->in_dtype, mk->ld_y, h->M, mk->d, cd, h->kpad,
-                    h->yop, h->yscale, h->ynorm, h->ctl, s) != hipSuccess)
+    const float ps = fused_prescale(mk->sigma);
+    if (launch_pack(mk->U, mk->Q, mk->in_dtype, mk->ld_x, h->N, mk->d, cd, h->kpad, ps,
+                    h->xop, h->xscale, h->ctl, s) != hipSuccess ||
+        launch_pack(mk->V, mk->P, mk->in_dtype, mk->ld_y, h->M, mk->d, cd, h->kpad, ps,
+                    h->yop, h->yscale, h->ctl, s) != hipSuccess)
       return fail(IPFP_EHIP);
-    FusedSide X{h->xop, cd == IPFP_FP8E4M3 ? h->xscale : nullptr, h->xnorm, h->N};
-    FusedSide Y{h->yop, cd == IPFP_FP8E4M3 ? h->yscale : nullptr, h->ynorm, h->M};
+    FusedSide X{h->xop, cd == IPFP_FP8E4M3 ? h->xscale : nullptr, h->N};
+    FusedSide Y{h->yop, cd == IPFP_FP8E4M3 ? h->yscale : nullptr, h->M};
     FusedPass& r = h->rowp;
-    r.out = X; r.red = Y; r.compute = cd; r.kpad = h->kpad; r.c = c;
-    r.bias = h->lv; r.shift = h->xshift; r.marg = mk->n; r.lw_new = h->lu;
+    r.out = X; r.red = Y; r.compute = cd; r.kpad = h->kpad;
+    r.w_red = h->v; r.red_dbuf = 0; r.exp_red = 1; r.exp_out = 0;
+    r.shift = h->xshift; r.marg = mk->n;
     r.part = h->xpart; r.res_block = h->res_block; r.fix_list = h->xfix;
     r.residual = true;
     FusedPass& q = h->colp;
-    q.out = Y; q.red = X; q.compute = cd; q.kpad = h->kpad; q.c = c;
-    q.bias = h->lu; q.shift = h->yshift; q.marg = mk->m; q.lw_new = h->lv;
+    q.out = Y; q.red = X; q.compute = cd; q.kpad = h->kpad;
+    q.w_red = h->u2; q.red_dbuf = 1; q.exp_red = 0; q.exp_out = 1;
+    q.shift = h->yshift; q.marg = mk->m;
     q.part = h->ypart; q.res_block = h->res_dummy; q.fix_list = h->yfix;
     q.residual = false;
-    // first-pass shifts from the Cauchy-Schwarz bound: row side against the
-    // initial v, column side against u <= sqrt(max n)
-    if (launch_log2_vec(h->v, h->lv, h->M, s) != hipSuccess ||
-        launch_initial_shift(X, Y, c, 1.0, h->v, h->M, h->xshift, h->tmp, s) != hipSuccess ||
-        launch_initial_shift(Y, X, c, 0.5, mk->n, h->N, h->yshift, h->tmp + 2, s) != hipSuccess)
+    // fixed row shifts h = -max T from one max pass per side; exponent of v0
+    if (launch_fused_shift(r, h->ctl, s) != hipSuccess ||
+        launch_fused_shift(q, h->ctl, s) != hipSuccess ||
+        launch_init_exp(h->v, h->M, h->ctl, 1, s) != hipSuccess)
       return fail(IPFP_EHIP);
   }
   if (read_ctl(h, s) != IPFP_OK) return fail(IPFP_EHIP);
@@ -645,8 +638,10 @@ int ipfp_mu_pairs(ipfp_ctx* ctx, const ipfp_market* mk, const double* a,
 
 int ipfp_pack_side(ipfp_ctx* ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
                    const void* A, const void* B, int64_t ld, ipfp_dtype compute,
-                   void* out, float* scale_out, int64_t* kpad_out, void* stream) {
+                   double sigma, void* out, float* scale_out, int64_t* kpad_out,
+                   void* stream) {
   if (!ctx || !kpad_out || rows < 1 || d < 1 || d > 128 || ld < d) return IPFP_EINVAL;
+  if (!(sigma >= 0.0) || !(sigma < INFINITY)) return IPFP_EINVAL;
   if (compute != IPFP_BF16 && compute != IPFP_FP8E4M3) return IPFP_EINVAL;
   const int64_t kpad = fused_kpad(d, compute);
   *kpad_out = kpad;
@@ -657,16 +652,15 @@ int ipfp_pack_side(ipfp_ctx* ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
   hipStream_t s = (hipStream_t)stream;
   if (hipSetDevice(ctx->device) != hipSuccess) return IPFP_EHIP;
   char* mem = nullptr;
-  const size_t bytes = align_up(sizeof(Ctl), 256) + rows * sizeof(float) * 2;
+  const size_t bytes = align_up(sizeof(Ctl), 256) + rows * sizeof(float);
   HIPCHK(hipMalloc((void**)&mem, bytes));
   Ctl* ctl = (Ctl*)mem;
-  float* norm = (float*)(mem + align_up(sizeof(Ctl), 256));
-  float* sc = scale_out ? scale_out : norm + rows;
+  float* sc = scale_out ? scale_out : (float*)(mem + align_up(sizeof(Ctl), 256));
   Ctl hc{};
   int rc = IPFP_OK;
   if (hipMemsetAsync(ctl, 0, sizeof(Ctl), s) != hipSuccess ||
-      launch_pack(A, B, in_dtype, ld, rows, d, compute, kpad, out, sc, norm, ctl, s) !=
-          hipSuccess ||
+      launch_pack(A, B, in_dtype, ld, rows, d, compute, kpad, fused_prescale(sigma), out,
+                  sc, ctl, s) != hipSuccess ||
       hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     rc = IPFP_EHIP;

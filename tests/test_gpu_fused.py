@@ -23,21 +23,16 @@ def lib():
     return L
 
 
-def quantised(mk, compute):
-    """Oracle-side values of the packed operands, as float64 U,Q,V,P."""
-    if compute == "bf16":
-        return tuple(quant.bf16_round(t).astype(np.float64) for t in (mk.U, mk.Q, mk.V, mk.P))
-    X = np.concatenate([mk.U, mk.Q], 1).astype(np.float64)
-    Y = np.concatenate([mk.V, mk.P], 1).astype(np.float64)
-    Xq, _ = quant.e4m3_quantize_rows(X)
-    Yq, _ = quant.e4m3_quantize_rows(Y)
-    d = mk.d
-    return Xq[:, :d], Xq[:, d:], Yq[:, :d], Yq[:, d:]
+# sigma with log2(e) / (2 sigma) = 1: the operand prescale is exactly 1, so
+# BF16-exact factors reach the matrix cores unchanged
+SIGMA_UNIT = 0.7213475204444817
 
 
 def oracle_quantised(mk, compute, sweeps, check_every=1, tol=0.0):
-    U, Q, V, P = quantised(mk, compute)
-    K = O.kernel_matrix(O.surplus_from_factors(U, Q, V, P), mk.sigma)
+    """Oracle fed the fused path's operand values: K = 2^(Xq Yq^T)."""
+    X = quant.packed_rows(np.concatenate([mk.U, mk.Q], 1), mk.sigma, compute)
+    Y = quant.packed_rows(np.concatenate([mk.V, mk.P], 1), mk.sigma, compute)
+    K = O.kernel_from_log2(X @ Y.T)
     return K, O.ipfp_batch(K, mk.n, mk.m, tol=tol, max_sweeps=sweeps, check_every=check_every)
 
 
@@ -48,19 +43,24 @@ def test_pack_side_is_bit_exact(torch, lib, compute):
     A = np.concatenate([mk.U[:, :5] * 50.0, mk.U[:, 5:] * 1e-3], 1).astype(np.float32)
     A[0] = 0.0
     B = mk.Q
-    codes, scale = lib.pack_side(to_dev(torch, A), to_dev(torch, B), compute)
     X = np.concatenate([A, B], 1)
-    kp = codes.shape[1]
-    if compute == "bf16":
-        want = np.zeros((777, kp), np.uint16)
-        want[:, :64] = quant.bf16_bits(X)
-        assert np.array_equal(codes.cpu().numpy().view(np.uint16), want)
-    else:
-        Xq, s = quant.e4m3_quantize_rows(X.astype(np.float64))
-        want = np.zeros((777, kp), np.uint8)
-        want[:, :64] = quant.e4m3_codes(Xq / s[:, None])
-        assert np.array_equal(scale.cpu().numpy().astype(np.float64), s)
-        assert np.array_equal(codes.cpu().numpy(), want)
+    for sigma in (0.0, 0.5, 1.3):
+        codes, scale = lib.pack_side(to_dev(torch, A), to_dev(torch, B), compute, sigma=sigma)
+        kp = codes.shape[1]
+        xs = X * quant.prescale(sigma)        # float32 multiply, as the packer does
+        if compute == "bf16":
+            want = np.zeros((777, kp), np.uint16)
+            want[:, :64] = quant.bf16_bits(xs)
+            assert np.array_equal(codes.cpu().numpy().view(np.uint16), want)
+            got = (codes.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+        else:
+            Xq, s = quant.e4m3_quantize_rows(xs.astype(np.float64))
+            want = np.zeros((777, kp), np.uint8)
+            want[:, :64] = quant.e4m3_codes(Xq / s[:, None])
+            assert np.array_equal(scale.cpu().numpy().astype(np.float64), s)
+            assert np.array_equal(codes.cpu().numpy(), want)
+            got = quant.e4m3_value_table()[codes.cpu().numpy()] * s[:, None]
+        np.testing.assert_array_equal(got[:, :64], quant.packed_rows(X, sigma, compute))
 
 
 @pytest.mark.parametrize("N,M,d", [(1, 1, 16), (2, 31, 16), (33, 257, 32), (257, 33, 32),
@@ -108,7 +108,7 @@ def test_fused_equals_plain_on_same_surplus(torch, lib):
     """Sec. 3.3: the mini-batch form makes no approximation. With BF16-exact
     factors both paths see the same Phi."""
     banner("fused vs plain")
-    mk = workloads.config_market(2, N=2000, M=1500)
+    mk = workloads.config_market(2, N=2000, M=1500, sigma=SIGMA_UNIT)
     for t in (mk.U, mk.Q, mk.V, mk.P):
         t[...] = quant.bf16_round(t)
     U, Q, V, P, n, m = market_tensors(torch, mk)
@@ -134,8 +134,8 @@ def test_fused_deterministic_and_split_independent(torch, lib):
 
 
 def test_fused_uniform_market_closed_form(torch, lib):
-    """Constant surplus c (BF16-exact): the converged scalings solve the
-    uniform market's quadratic."""
+    """Constant surplus c (BF16-exact, unit prescale): the converged scalings
+    solve the uniform market's quadratic."""
     banner("fused uniform closed form")
     N, M, d = 3000, 2000, 8
     U = np.zeros((N, d), np.float32)
@@ -144,10 +144,10 @@ def test_fused_uniform_market_closed_form(torch, lib):
     V[:, 0] = 1.0
     Z = np.zeros_like(U)
     W = np.zeros_like(V)
-    mu, u, v = closed.uniform_market(0.75, 1.0, 2.0, N, M, 1.0)
+    mu, u, v = closed.uniform_market(0.75, 1.0, 2.0, N, M, SIGMA_UNIT)
     a, b, info = lib.solve_market(to_dev(torch, U), to_dev(torch, Z), to_dev(torch, V),
                                   to_dev(torch, W), to_dev(torch, np.ones(N)),
-                                  to_dev(torch, np.full(M, 2.0)), 1.0, tol=1e-9,
+                                  to_dev(torch, np.full(M, 2.0)), SIGMA_UNIT, tol=1e-9,
                                   max_sweeps=3000)
     assert rel_err(a.cpu().numpy(), np.full(N, u)) < 1e-5
     assert rel_err(b.cpu().numpy(), np.full(M, v)) < 1e-5
@@ -167,26 +167,25 @@ def test_fused_separable_replay(torch, lib):
     V[:, 0], V[:, 1] = 1.0, ga
     n = np.ones(N)
     m = rng.integers(1, 6, M).astype(np.float64)
-    r = closed.separable_replay(al, ga, n, m, 0.5, max_sweeps=25, check_every=5)
+    r = closed.separable_replay(al, ga, n, m, SIGMA_UNIT, max_sweeps=25, check_every=5)
     a, b, info = lib.solve_market(to_dev(torch, U), to_dev(torch, np.zeros_like(U)),
                                   to_dev(torch, V), to_dev(torch, np.zeros_like(V)),
-                                  to_dev(torch, n), to_dev(torch, m), 0.5, max_sweeps=25,
-                                  check_every=5)
+                                  to_dev(torch, n), to_dev(torch, m), SIGMA_UNIT,
+                                  max_sweeps=25, check_every=5)
     assert rel_err(a.cpu().numpy(), r.a) < 2e-5
     assert rel_err(b.cpu().numpy(), r.b) < 2e-5
 
 
 def test_fused_exact_shift_fallback(torch, lib):
-    """Orthogonal factors of large norm: the Cauchy-Schwarz first shift is
-    ~300 binades too low, every first-pass sum underflows and the exact-shift
-    fallback must recompute those rows."""
+    """Rows whose largest surplus sits on a column with a tiny scaling: every
+    shifted term 2^(T - max T) w~ of those rows is below 2^-60, so the combine
+    must hand them to the exact two-pass fallback."""
     banner("fused fixup")
-    N, M, d = 300, 200, 8
-    mk = workloads.factor_market(N, M, d, 1.0 / d, 1.0, "unit", seed=11)
-    mk.U[:, 0] = 20.0
-    mk.V[:, 1] = 20.0
-    mk.U[:, 1] = 0.0
-    mk.V[:, 0] = 0.0
+    N, M, d = 40, 30, 4
+    mk = workloads.factor_market(N, M, d, 0.01, 0.05, "unit", seed=11)
+    mk.U[:10, 0] = 3.0
+    mk.V[0, 0] = 3.5            # Phi(x<10, 0) ~ 10.5, T ~ 150 binades above the rest
+    mk.m[0] = 1e-40             # v_0 <= 1e-20: far below the other columns' v
     U, Q, V, P, n, m = market_tensors(torch, mk)
     a, b, info = lib.solve_market(U, Q, V, P, n, m, mk.sigma, max_sweeps=10)
     assert info.fixups > 0

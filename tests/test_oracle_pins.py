@@ -350,3 +350,22 @@ def test_mutations_are_caught():
     p = brute.primal_newton(Phi[:, :4], n, m[:4], beta)
     mu, mx0 = transposed(Phi, n, m, beta)
     assert not np.allclose(mu, p.mu, rtol=1e-8)
+
+
+def test_packed_rows_reduce_to_plain_rounding_and_log2_kernel():
+    """With unit prescale packed_rows is exactly the BF16 / e4m3 rounding, and
+    2^(X Y^T) with the prescaled operands approximates exp(Phi / 2 sigma) to
+    the operand rounding (each of the 2d products carries <= 2^-8 relative)."""
+    rng = np.random.default_rng(21)
+    X = rng.normal(0, 0.2, (30, 16)).astype(np.float32)
+    Y = rng.normal(0, 0.2, (20, 16)).astype(np.float32)
+    assert np.array_equal(quant.packed_rows(X, 0.0, "bf16"), quant.bf16_round(X).astype(np.float64))
+    assert np.array_equal(quant.packed_rows(X, 0.0, "fp8"), quant.e4m3_quantize_rows(X)[0])
+    assert quant.prescale(np.log2(np.e) / 2) == np.float32(1.0)
+    for sigma in (0.3, 1.0):
+        Xq = quant.packed_rows(X, sigma, "bf16")
+        Yq = quant.packed_rows(Y, sigma, "bf16")
+        K2 = ipfp.kernel_from_log2(Xq @ Yq.T)
+        K = ipfp.kernel_matrix(X.astype(np.float64) @ Y.astype(np.float64).T, sigma)
+        bound = np.abs(X.astype(np.float64)) @ np.abs(Y.astype(np.float64)).T / (2 * sigma)
+        assert np.all(np.abs(np.log(K2 / K)) <= 2 * 2.0 ** -8 * bound + 1e-12)
