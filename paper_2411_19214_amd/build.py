@@ -24,7 +24,7 @@ SOURCES = ["control.hip", "plain.hip", "fused.hip", "runtime.hip"]
 
 ARCH = "gfx950"
 HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}",
 ]

@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256)
   float amax = 0.f;
   for (int64_t k = lane; k < k2; k += 64) {
     const float x = val(k);
-    finite &= (x - x == 0.f);
+    finite &= __builtin_isfinite(x);
     amax = fmaxf(amax, fabsf(x));
   }
   if (!finite) atomicOr(&ctl->nonfinite, 1);
@@ -404,7 +404,7 @@ __device__ __forceinline__ double finish_row(int64_t o, double lS,
     res = fabs(fma(wo, wo, -nx) + two_s_wo) / nx;
   }
   const double w = lS < 1000.0 ? quad_root(nx, exp2(lS - 1.0)) : nx * exp2(-lS);
-  if (!(w - w == 0.0)) atomicOr(&ctl->nonfinite, 1);
+  if (!__builtin_isfinite(w)) atomicOr(&ctl->nonfinite, 1);
   w_new[o] = w;
   return res;
 }

@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256)
   bool finite = true;
   for (int64_t y = threadIdx.x; y < M; y += 256) {
     double p = (double)row[y];
-    finite &= (p - p == 0.0);
+    finite &= __builtin_isfinite(p);
     mx = p > mx ? p : mx;
   }
   if (!finite) atomicOr(&ctl->nonfinite, 1);
@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(256)
       const double uo = u_old[x], nx = n[x];
       res = fabs(fma(uo, uo, -nx) + 2.0 * uo * s) / nx;
       const double un = quad_root(nx, s);
-      if (!(un - un == 0.0)) atomicOr(&ctl->nonfinite, 1);
+      if (!__builtin_isfinite(un)) atomicOr(&ctl->nonfinite, 1);
       u_new[x] = un;
       ut[x] = ec * un;
     }
@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(256)
   double S = 0.0;
   for (int k = 0; k < splits; ++k) S += part[(int64_t)k * M + y];
   const double vn = quad_root(m[y], 0.5 * S);
-  if (!(vn - vn == 0.0)) atomicOr(&ctl->nonfinite, 1);
+  if (!__builtin_isfinite(vn)) atomicOr(&ctl->nonfinite, 1);
   v[y] = vn;
 }
 
