@@ -170,6 +170,16 @@ struct Op<true> {  // FP8 e4m3, v_mfma_scale_f32_32x32x64_f8f6f4
 #endif
 constexpr int ty_for(int row_bytes) { return row_bytes <= 256 ? IPFP_TY : IPFP_TY / 2; }
 
+// Software-pipelined epilogue (1) and explicit MFMA/exp2/FMA interleaving
+// hints (1); build-time knobs.
+#ifndef IPFP_PIPE
+#define IPFP_PIPE 1
+#endif
+#ifndef IPFP_SCHED
+#define IPFP_SCHED 1
+#endif
+constexpr bool kPipe = IPFP_PIPE != 0;
+
 // Binary exponent e with w = m 2^e, m in [0.5, 1) (INT_MIN for w = 0).
 __device__ __forceinline__ int exponent_of(double w) {
   if (!(w > 0.0)) return INT_MIN;
@@ -296,6 +306,28 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
     if (FP8) ysc[buf][tid % kTY] = psc;
   };
 
+  // exp2 of 16 accumulator entries times their weights, summed in two FMA
+  // chains of 8, added to the lane's FP64 running sum
+  auto epilogue = [&](const floatx16& a, const float* w, double& acc_run) {
+    float s0 = __builtin_amdgcn_exp2f(a[0]) * w[0];
+    float s1 = __builtin_amdgcn_exp2f(a[1]) * w[1];
+#pragma unroll
+    for (int r = 2; r < 16; r += 2) {
+      s0 = fmaf(__builtin_amdgcn_exp2f(a[r]), w[r], s0);
+      s1 = fmaf(__builtin_amdgcn_exp2f(a[r + 1]), w[r + 1], s1);
+    }
+    acc_run += (double)(s0 + s1);
+  };
+  // pending accumulator of the software pipeline (a dummy of zero weight
+  // before the first tile)
+  floatx16 accp;
+  float wp[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    accp[r] = 0.f;
+    wp[r] = 0.f;
+  }
+
   if (t0 < t1) {
     gload(t0);
     lstore(0);
@@ -357,22 +389,30 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
             m1 = fmaxf(m1, acc[r + 1]);
           }
           mx[t] = fmaxf(mx[t], fmaxf(m0, m1));
-        } else {
-          // two FMA chains of 8 for instruction-level parallelism
-          float s0 = __builtin_amdgcn_exp2f(acc[0]) * wv[0];
-          float s1 = __builtin_amdgcn_exp2f(acc[1]) * wv[1];
+        } else if constexpr (kPipe) {
+          // the previous accumulator's exp2/FMA work runs while the matrix
+          // cores compute this one (transcendentals co-issue with MFMA)
+          epilogue(accp, wp, run[t == 0 ? XT - 1 : t - 1]);
+#if IPFP_SCHED
 #pragma unroll
-          for (int r = 2; r < 16; r += 2) {
-            s0 = fmaf(__builtin_amdgcn_exp2f(acc[r]), wv[r], s0);
-            s1 = fmaf(__builtin_amdgcn_exp2f(acc[r + 1]), wv[r + 1], s1);
+          for (int s = 0; s < NS; ++s) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);               // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x400, 16 / NS, 0);         // exp2
+            __builtin_amdgcn_sched_group_barrier(0x002, 16 / NS, 0);         // FMA
           }
-          run[t] += (double)(s0 + s1);
+#endif
+          accp = acc;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) wp[r] = wv[r];
+        } else {
+          epilogue(acc, wv, run[t]);
         }
       }
     }
     lstore(buf ^ 1);
     __syncthreads();
   }
+  if constexpr (!MAXMODE && kPipe) epilogue(accp, wp, run[XT - 1]);
 
 #pragma unroll
   for (int t = 0; t < XT; ++t) {
