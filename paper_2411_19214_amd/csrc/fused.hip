@@ -162,23 +162,13 @@ struct Op<true> {  // FP8 e4m3, v_mfma_scale_f32_32x32x64_f8f6f4
   static constexpr int ES = 1, SB = 32, KS = 64;
 };
 
-// Reduced rows staged per LDS buffer (a multiple of 32): IPFP_TY (a build-time
+// Reduced rows staged per LDS buffer (a multiple of 64): IPFP_TY (a build-time
 // knob) for packed rows up to 256 bytes, half of it for longer rows so that
 // the double buffer stays near 70 KiB of LDS.
 #ifndef IPFP_TY
 #define IPFP_TY 128
 #endif
 constexpr int ty_for(int row_bytes) { return row_bytes <= 256 ? IPFP_TY : IPFP_TY / 2; }
-
-// Software-pipelined epilogue (1) and explicit MFMA/exp2/FMA interleaving
-// hints (1); build-time knobs.
-#ifndef IPFP_PIPE
-#define IPFP_PIPE 1
-#endif
-#ifndef IPFP_SCHED
-#define IPFP_SCHED 1
-#endif
-constexpr bool kPipe = IPFP_PIPE != 0;
 
 // Binary exponent e with w = m 2^e, m in [0.5, 1) (INT_MIN for w = 0).
 __device__ __forceinline__ int exponent_of(double w) {
@@ -188,8 +178,61 @@ __device__ __forceinline__ int exponent_of(double w) {
   return e;
 }
 
-// MAXMODE: per (split, row) maximum of T over the split (set-up pass);
-// otherwise the weighted sum S described at the top of this file.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Everything a reduction pass keeps per wave, plus the staging of the reduced
+// side through LDS; shared by the max pass and the sum pass.
+template <int KP, int XT, int WAVES, bool FP8>
+struct PassCore {
+  typedef Op<FP8> O;
+  static constexpr int RB = KP * O::ES;           // bytes per packed row
+  static constexpr int kTY = ty_for(RB);          // reduced rows per stage
+  static constexpr int NS = KP / O::KS;           // MFMAs per 32x32 tile
+  static constexpr int LS = RB + 16;              // LDS row stride (pad)
+  static constexpr int NT = WAVES * 64;
+  static constexpr int CH = kTY * RB / 16;        // 16-byte chunks per stage
+  static constexpr int CPT = (CH + NT - 1) / NT;  // chunks per thread
+  static constexpr int SUB = kTY / 32;
+  typedef typename std::conditional<FP8, intx8, bf16x8>::type Frag;
+};
+
+// Reads the A fragment of k-step s for reduced row `row` of a staged tile.
+template <bool FP8, typename Frag>
+__device__ __forceinline__ Frag lds_frag(const uint8_t* arow, int s) {
+  typedef Op<FP8> O;
+  Frag f;
+  if constexpr (FP8) {
+    intx4 lo = *reinterpret_cast<const intx4*>(arow + s * 2 * O::SB);
+    intx4 hi = *reinterpret_cast<const intx4*>(arow + s * 2 * O::SB + 16);
+    intx8 v;
+    v[0] = lo[0]; v[1] = lo[1]; v[2] = lo[2]; v[3] = lo[3];
+    v[4] = hi[0]; v[5] = hi[1]; v[6] = hi[2]; v[7] = hi[3];
+    *reinterpret_cast<intx8*>(&f) = v;
+  } else {
+    *reinterpret_cast<intx4*>(&f) = *reinterpret_cast<const intx4*>(arow + s * 2 * O::SB);
+  }
+  return f;
+}
+
+template <bool FP8, typename Frag>
+__device__ __forceinline__ floatx16 mfma_step(const Frag& a, const Frag& b, floatx16 c,
+                                              int asc, int bsc) {
+  if constexpr (FP8)
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+        *reinterpret_cast<const intx8*>(&a), *reinterpret_cast<const intx8*>(&b), c, 0, 0,
+        0, asc, 0, bsc);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// The reduction pass. MAXMODE: per (split, row) maximum of T over the split
+// (set-up). Otherwise the weighted sum S described at the top of this file.
+//
+// Sum mode runs two independent accumulators ("chains") at a time -- the two
+// output tiles of a wave (XT = 2) or two consecutive reduced subtiles (XT =
+// 1) -- so consecutive MFMAs never wait on each other, and the exp2/FMA
+// epilogue of the previous pair is spread between this pair's MFMAs: the
+// matrix cores and the transcendental/FMA pipe then work at the same time.
 template <int KP, int XT, int WAVES, bool FP8, bool MAXMODE>
 __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
     k_fused_pass(const uint8_t* __restrict__ Xo, const float* __restrict__ xscale,
@@ -198,18 +241,15 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
                  int exp_out, const float* __restrict__ shift, int R, int L,
                  int tiles_per_split, int nsplit, double* __restrict__ part,
                  Ctl* ctl) {
+  typedef PassCore<KP, XT, WAVES, FP8> C;
+  typedef typename C::Frag Frag;
   typedef Op<FP8> O;
-  constexpr int RB = KP * O::ES;           // bytes per packed row
-  constexpr int kTY = ty_for(RB);
-  constexpr int NS = KP / O::KS;           // MFMAs per 32x32 output tile
-  constexpr int LS = RB + 16;              // LDS row stride (bank-conflict pad)
-  constexpr int NT = WAVES * 64;
-  constexpr int CH = kTY * RB / 16;        // 16-byte chunks per stage
-  constexpr int CPT = (CH + NT - 1) / NT;  // chunks per thread
-  constexpr int SUB = kTY / 32;
+  constexpr int RB = C::RB, kTY = C::kTY, NS = C::NS, LS = C::LS, NT = C::NT;
+  constexpr int CH = C::CH, CPT = C::CPT, SUB = C::SUB;
 
   __shared__ __attribute__((aligned(16))) uint8_t ys[2][kTY * LS];
   __shared__ __attribute__((aligned(16))) float ws[2][kTY];
+  __shared__ __attribute__((aligned(16))) float wzero[32];
   __shared__ int32_t ysc[2][kTY];          // FP8: E8M0 scale byte per row
 
   if (ctl->done) return;
@@ -231,9 +271,9 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
   const int t0 = split * tiles_per_split;
   const int t1 = min(T, t0 + tiles_per_split);
   const int row_base = (rb * WAVES + wave) * (XT * 32);
+  if (tid < 32) wzero[tid] = 0.f;
 
   // output-side operand fragments, shift accumulators and scales (registers)
-  typedef typename std::conditional<FP8, intx8, bf16x8>::type Frag;
   Frag bfrag[XT][NS];
   floatx16 shv[XT];
   int xsc[XT];
@@ -244,17 +284,12 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
     const uint8_t* src = Xo + (int64_t)(ok ? x : 0) * RB + h * O::SB;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      if (FP8) {
-        intx4 lo = ok ? *reinterpret_cast<const intx4*>(src + s * 2 * O::SB) : intx4{0, 0, 0, 0};
-        intx4 hi = ok ? *reinterpret_cast<const intx4*>(src + s * 2 * O::SB + 16) : intx4{0, 0, 0, 0};
-        intx8 v;
-        v[0] = lo[0]; v[1] = lo[1]; v[2] = lo[2]; v[3] = lo[3];
-        v[4] = hi[0]; v[5] = hi[1]; v[6] = hi[2]; v[7] = hi[3];
-        *reinterpret_cast<intx8*>(&bfrag[t][s]) = v;
-      } else {
-        intx4 v = ok ? *reinterpret_cast<const intx4*>(src + s * 2 * O::SB) : intx4{0, 0, 0, 0};
-        *reinterpret_cast<intx4*>(&bfrag[t][s]) = v;
+      Frag f = lds_frag<FP8, Frag>(src, s);   // same layout as a staged row
+      if (!ok) *reinterpret_cast<intx4*>(&f) = intx4{0, 0, 0, 0};
+      if constexpr (FP8) {
+        if (!ok) reinterpret_cast<intx4*>(&f)[1] = intx4{0, 0, 0, 0};
       }
+      bfrag[t][s] = f;
     }
     const float hv = (!MAXMODE && ok) ? shift[x] : 0.f;
 #pragma unroll
@@ -306,27 +341,43 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
     if (FP8) ysc[buf][tid % kTY] = psc;
   };
 
-  // exp2 of 16 accumulator entries times their weights, summed in two FMA
-  // chains of 8, added to the lane's FP64 running sum
-  auto epilogue = [&](const floatx16& a, const float* w, double& acc_run) {
-    float s0 = __builtin_amdgcn_exp2f(a[0]) * w[0];
-    float s1 = __builtin_amdgcn_exp2f(a[1]) * w[1];
-#pragma unroll
-    for (int r = 2; r < 16; r += 2) {
-      s0 = fmaf(__builtin_amdgcn_exp2f(a[r]), w[r], s0);
-      s1 = fmaf(__builtin_amdgcn_exp2f(a[r + 1]), w[r + 1], s1);
-    }
-    acc_run += (double)(s0 + s1);
-  };
-  // pending accumulator of the software pipeline (a dummy of zero weight
-  // before the first tile)
-  floatx16 accp;
-  float wp[16];
+  // sum mode: the pending pair of accumulators, their weights (LDS; a buffer
+  // is overwritten only after the following tile, so they are still there)
+  // and their running-sum slots; a zero-weight dummy before the first tile
+  constexpr int NPAIR = XT == 2 ? SUB : SUB / 2;
+  floatx16 pc0, pc1;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    accp[r] = 0.f;
-    wp[r] = 0.f;
+    pc0[r] = 0.f;
+    pc1[r] = 0.f;
   }
+  const float* pw0 = &wzero[4 * h];
+  const float* pw1 = pw0;
+  // exp2/FMA of the pending pair's entries [r0, r1) into four partial sums
+  auto epi = [&](int r0, int r1, const float* w0, const float* w1, float* s4) {
+#pragma unroll
+    for (int r = r0; r < r1; ++r) {
+      const float e0 = __builtin_amdgcn_exp2f(pc0[r]);
+      const float e1 = __builtin_amdgcn_exp2f(pc1[r]);
+      s4[r & 1] = fmaf(e0, w0[r], s4[r & 1]);
+      s4[2 + (r & 1)] = fmaf(e1, w1[r], s4[2 + (r & 1)]);
+    }
+  };
+  auto load_w = [&](const float* p, float* w) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const floatx4 w4 = *reinterpret_cast<const floatx4*>(p + 8 * g);
+      w[4 * g + 0] = w4[0];
+      w[4 * g + 1] = w4[1];
+      w[4 * g + 2] = w4[2];
+      w[4 * g + 3] = w4[3];
+    }
+  };
+  auto flush = [&](const float* s4) {
+    // the pending pair's tiles: (t = 0, 1) for XT = 2, both tile 0 for XT = 1
+    run[0] += (double)(s4[0] + s4[1]);
+    run[XT - 1] += (double)(s4[2] + s4[3]);
+  };
 
   if (t0 < t1) {
     gload(t0);
@@ -337,51 +388,17 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
   for (int tile = t0; tile < t1; ++tile) {
     const int buf = (tile - t0) & 1;
     gload(min(tile + 1, t1 - 1));   // prefetch (the last iteration reloads harmlessly)
+    if constexpr (MAXMODE) {
 #pragma unroll
-    for (int sub = 0; sub < SUB; ++sub) {
-      const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
-      Frag afrag[NS];
+      for (int sub = 0; sub < SUB; ++sub) {
+        const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
+        const int asc = FP8 ? ysc[buf][sub * 32 + l32] : 127;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        if (FP8) {
-          intx4 lo = *reinterpret_cast<const intx4*>(arow + s * 2 * O::SB);
-          intx4 hi = *reinterpret_cast<const intx4*>(arow + s * 2 * O::SB + 16);
-          intx8 v;
-          v[0] = lo[0]; v[1] = lo[1]; v[2] = lo[2]; v[3] = lo[3];
-          v[4] = hi[0]; v[5] = hi[1]; v[6] = hi[2]; v[7] = hi[3];
-          *reinterpret_cast<intx8*>(&afrag[s]) = v;
-        } else {
-          *reinterpret_cast<intx4*>(&afrag[s]) =
-              *reinterpret_cast<const intx4*>(arow + s * 2 * O::SB);
-        }
-      }
-      const int asc = FP8 ? ysc[buf][sub * 32 + l32] : 127;
-      // weights of the 16 reduced rows this lane holds: 8 g + 4 h + (0..3)
-      float wv[16];
-      if (!MAXMODE) {
+        for (int t = 0; t < XT; ++t) {
+          floatx16 acc = shv[t];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          float4 w4 = *reinterpret_cast<const float4*>(&ws[buf][sub * 32 + 8 * g + 4 * h]);
-          wv[4 * g + 0] = w4.x;
-          wv[4 * g + 1] = w4.y;
-          wv[4 * g + 2] = w4.z;
-          wv[4 * g + 3] = w4.w;
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < XT; ++t) {
-        floatx16 acc = shv[t];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          if constexpr (FP8) {
-            acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                *reinterpret_cast<intx8*>(&afrag[s]), *reinterpret_cast<intx8*>(&bfrag[t][s]),
-                acc, 0, 0, 0, asc, 0, xsc[t]);
-          } else {
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afrag[s], bfrag[t][s], acc, 0, 0, 0);
-          }
-        }
-        if constexpr (MAXMODE) {
+          for (int s = 0; s < NS; ++s)
+            acc = mfma_step<FP8>(lds_frag<FP8, Frag>(arow, s), bfrag[t][s], acc, asc, xsc[t]);
           float m0 = fmaxf(acc[0], acc[1]), m1 = fmaxf(acc[2], acc[3]);
 #pragma unroll
           for (int r = 4; r < 16; r += 2) {
@@ -389,30 +406,53 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
             m1 = fmaxf(m1, acc[r + 1]);
           }
           mx[t] = fmaxf(mx[t], fmaxf(m0, m1));
-        } else if constexpr (kPipe) {
-          // the previous accumulator's exp2/FMA work runs while the matrix
-          // cores compute this one (transcendentals co-issue with MFMA)
-          epilogue(accp, wp, run[t == 0 ? XT - 1 : t - 1]);
-#if IPFP_SCHED
-#pragma unroll
-          for (int s = 0; s < NS; ++s) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);               // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x400, 16 / NS, 0);         // exp2
-            __builtin_amdgcn_sched_group_barrier(0x002, 16 / NS, 0);         // FMA
-          }
-#endif
-          accp = acc;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) wp[r] = wv[r];
-        } else {
-          epilogue(acc, wv, run[t]);
         }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NPAIR; ++q) {
+        const int sub0 = XT == 2 ? q : 2 * q, sub1 = XT == 2 ? q : 2 * q + 1;
+        constexpr int ta = 0, tb = XT - 1;
+        const uint8_t* arow0 = &ys[buf][(sub0 * 32 + l32) * LS + h * O::SB];
+        const uint8_t* arow1 = &ys[buf][(sub1 * 32 + l32) * LS + h * O::SB];
+        const int asc0 = FP8 ? ysc[buf][sub0 * 32 + l32] : 127;
+        const int asc1 = FP8 ? ysc[buf][sub1 * 32 + l32] : 127;
+        float w0[16], w1[16];
+        load_w(pw0, w0);
+        if constexpr (XT == 2) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) w1[r] = w0[r];
+        } else {
+          load_w(pw1, w1);
+        }
+        float s4[4] = {0.f, 0.f, 0.f, 0.f};
+        floatx16 a0 = shv[ta], a1 = shv[tb];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const Frag f0 = lds_frag<FP8, Frag>(arow0, s);
+          const Frag f1 = XT == 2 ? f0 : lds_frag<FP8, Frag>(arow1, s);
+          a0 = mfma_step<FP8>(f0, bfrag[ta][s], a0, asc0, xsc[ta]);
+          a1 = mfma_step<FP8>(f1, bfrag[tb][s], a1, asc1, xsc[tb]);
+          epi(16 * s / NS, 16 * (s + 1) / NS, w0, w1, s4);
+        }
+        flush(s4);
+        pc0 = a0;
+        pc1 = a1;
+        pw0 = &ws[buf][sub0 * 32 + 4 * h];
+        pw1 = &ws[buf][sub1 * 32 + 4 * h];
       }
     }
     lstore(buf ^ 1);
     __syncthreads();
   }
-  if constexpr (!MAXMODE && kPipe) epilogue(accp, wp, run[XT - 1]);
+  if constexpr (!MAXMODE) {
+    float w0[16], w1[16];
+    load_w(pw0, w0);
+    load_w(pw1, w1);
+    float s4[4] = {0.f, 0.f, 0.f, 0.f};
+    epi(0, 16, w0, w1, s4);
+    flush(s4);
+  }
 
 #pragma unroll
   for (int t = 0; t < XT; ++t) {
