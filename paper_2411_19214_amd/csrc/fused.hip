@@ -248,7 +248,10 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
   constexpr int CH = C::CH, CPT = C::CPT, SUB = C::SUB;
 
   __shared__ __attribute__((aligned(16))) uint8_t ys[2][kTY * LS];
-  __shared__ __attribute__((aligned(16))) float ws[2][kTY];
+  // weights are triple-buffered: the pending epilogue reads a tile's weights
+  // during the following tile, while other waves may already be staging the
+  // tile after that
+  __shared__ __attribute__((aligned(16))) float ws[3][kTY];
   __shared__ __attribute__((aligned(16))) float wzero[32];
   __shared__ int32_t ysc[2][kTY];          // FP8: E8M0 scale byte per row
 
@@ -330,14 +333,14 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
     }
     if (FP8) psc = (int)((__float_as_uint(yscale[yc]) >> 23) & 0xFF);
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, int wbuf) {
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int chunk = min(tid + q * NT, CH - 1);
       const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
       *reinterpret_cast<intx4*>(&ys[buf][r * LS + cb * 16]) = pre[q];
     }
-    if (!MAXMODE) ws[buf][tid % kTY] = pw;
+    if (!MAXMODE) ws[wbuf][tid % kTY] = pw;
     if (FP8) ysc[buf][tid % kTY] = psc;
   };
 
@@ -381,12 +384,14 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
 
   if (t0 < t1) {
     gload(t0);
-    lstore(0);
+    lstore(0, 0);
   }
   __syncthreads();
 
+  int wbuf = 0;
   for (int tile = t0; tile < t1; ++tile) {
     const int buf = (tile - t0) & 1;
+    const int wnext = wbuf == 2 ? 0 : wbuf + 1;
     gload(min(tile + 1, t1 - 1));   // prefetch (the last iteration reloads harmlessly)
     if constexpr (MAXMODE) {
 #pragma unroll
@@ -438,11 +443,12 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
         flush(s4);
         pc0 = a0;
         pc1 = a1;
-        pw0 = &ws[buf][sub0 * 32 + 4 * h];
-        pw1 = &ws[buf][sub1 * 32 + 4 * h];
+        pw0 = &ws[wbuf][sub0 * 32 + 4 * h];
+        pw1 = &ws[wbuf][sub1 * 32 + 4 * h];
       }
     }
-    lstore(buf ^ 1);
+    lstore(buf ^ 1, wnext);
+    wbuf = wnext;
     __syncthreads();
   }
   if constexpr (!MAXMODE) {
