@@ -348,6 +348,9 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
   // is overwritten only after the following tile, so they are still there)
   // and their running-sum slots; a zero-weight dummy before the first tile
   constexpr int NPAIR = XT == 2 ? SUB : SUB / 2;
+  // the paired, pipelined schedule pays off where the MFMAs dominate a step
+  // (FP8 operands, BF16 with 2d = 128); elsewhere one chain at a time
+  constexpr bool kPaired = FP8 || KP == 128;
   floatx16 pc0, pc1;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -356,16 +359,14 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
   }
   const float* pw0 = &wzero[4 * h];
   const float* pw1 = pw0;
-  // exp2/FMA of the pending pair's entries [r0, r1) into four partial sums
-  auto epi = [&](int r0, int r1, const float* w0, const float* w1, float* s4) {
-#pragma unroll
-    for (int r = r0; r < r1; ++r) {
-      const float e0 = __builtin_amdgcn_exp2f(pc0[r]);
-      const float e1 = __builtin_amdgcn_exp2f(pc1[r]);
-      s4[r & 1] = fmaf(e0, w0[r], s4[r & 1]);
-      s4[2 + (r & 1)] = fmaf(e1, w1[r], s4[2 + (r & 1)]);
-    }
+  // exp2/FMA of pending entry r of both chains into four partial sums
+  auto epi1 = [&](const int r, const float* w0, const float* w1, float* s4) {
+    const float e0 = __builtin_amdgcn_exp2f(pc0[r]);
+    const float e1 = __builtin_amdgcn_exp2f(pc1[r]);
+    s4[r & 1] = fmaf(e0, w0[r], s4[r & 1]);
+    s4[2 + (r & 1)] = fmaf(e1, w1[r], s4[2 + (r & 1)]);
   };
+  constexpr int PER = (16 + NS - 1) / NS;   // pending entries per k-step
   auto load_w = [&](const float* p, float* w) {
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -413,6 +414,30 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
           mx[t] = fmaxf(mx[t], fmaxf(m0, m1));
         }
       }
+    } else if constexpr (!kPaired) {
+      // one accumulator at a time, its epilogue right after its MFMAs
+#pragma unroll
+      for (int sub = 0; sub < SUB; ++sub) {
+        const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
+        const int asc = FP8 ? ysc[buf][sub * 32 + l32] : 127;
+        float w[16];
+        load_w(&ws[wbuf][sub * 32 + 4 * h], w);
+#pragma unroll
+        for (int t = 0; t < XT; ++t) {
+          floatx16 acc = shv[t];
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+            acc = mfma_step<FP8>(lds_frag<FP8, Frag>(arow, s), bfrag[t][s], acc, asc, xsc[t]);
+          float s0 = __builtin_amdgcn_exp2f(acc[0]) * w[0];
+          float s1 = __builtin_amdgcn_exp2f(acc[1]) * w[1];
+#pragma unroll
+          for (int r = 2; r < 16; r += 2) {
+            s0 = fmaf(__builtin_amdgcn_exp2f(acc[r]), w[r], s0);
+            s1 = fmaf(__builtin_amdgcn_exp2f(acc[r + 1]), w[r + 1], s1);
+          }
+          run[t] += (double)(s0 + s1);
+        }
+      }
     } else {
 #pragma unroll
       for (int q = 0; q < NPAIR; ++q) {
@@ -438,7 +463,9 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
           const Frag f1 = XT == 2 ? f0 : lds_frag<FP8, Frag>(arow1, s);
           a0 = mfma_step<FP8>(f0, bfrag[ta][s], a0, asc0, xsc[ta]);
           a1 = mfma_step<FP8>(f1, bfrag[tb][s], a1, asc1, xsc[tb]);
-          epi(16 * s / NS, 16 * (s + 1) / NS, w0, w1, s4);
+#pragma unroll
+          for (int u = 0; u < PER; ++u)
+            if (s * PER + u < 16) epi1(s * PER + u, w0, w1, s4);
         }
         flush(s4);
         pc0 = a0;
@@ -451,12 +478,13 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
     wbuf = wnext;
     __syncthreads();
   }
-  if constexpr (!MAXMODE) {
+  if constexpr (!MAXMODE && kPaired) {
     float w0[16], w1[16];
     load_w(pw0, w0);
     load_w(pw1, w1);
     float s4[4] = {0.f, 0.f, 0.f, 0.f};
-    epi(0, 16, w0, w1, s4);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) epi1(r, w0, w1, s4);
     flush(s4);
   }
 
