@@ -37,7 +37,8 @@
  *    synchronise that stream before returning.
  *  - Matrices are row-major with a leading dimension (row stride) given in
  *    elements, >= the row length.
- *  - Inputs are validated before any launch: N, M >= 1; 1 <= d <= 256;
+ *  - Inputs are validated before any launch: N, M >= 1; 1 <= d <= 256
+ *    (fused path: d <= 128);
  *    sigma > 0 and finite; n and m must be > 0 and finite (checked on the
  *    device; a violation gives IPFP_EINVAL). Non-finite factor or surplus
  *    values give IPFP_ENONFINITE.
@@ -96,10 +97,10 @@ typedef struct {
 
 typedef struct {
   ipfp_path path;        /* FUSED (factors) or PLAIN (materialised K)         */
-  ipfp_dtype compute;    /* FUSED: BF16 or FP8E4M3 or F32 operands for the
-                            surplus tiles (FP32 accumulate, FP32 exp2, FP64
-                            sums and updates). PLAIN: F32 or F64 storage of K
-                            (FP64 sums and updates either way).               */
+  ipfp_dtype compute;    /* FUSED: BF16 or FP8E4M3 operands for the surplus
+                            tiles (FP32 accumulate, FP32 exp2, FP64 sums and
+                            updates). PLAIN: F32 or F64 storage of K (FP64
+                            sums and updates either way).                     */
   double tol;            /* stop when the row residual < tol; 0 = never       */
   int32_t max_sweeps;    /* >= 1                                              */
   int32_t check_every;   /* >= 1: residual cadence (and host sync cadence)    */
@@ -212,6 +213,85 @@ int ipfp_pack_side(ipfp_ctx *ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
                    const void *A, const void *B, int64_t ld, ipfp_dtype compute,
                    double sigma, void *out, float *scale_out, int64_t *kpad_out,
                    void *stream);
+
+/* ---- serving: continuous batching of many markets ------------------------
+ *
+ * The paper solves one market at a time; a server solves a stream of
+ * independent markets (requests) concurrently on one device. It owns one slab
+ * of device memory (its arena) and a scheduler thread. Requests are admitted
+ * in submission order while their footprint (ipfp_footprint) fits the arena
+ * and fewer than max_active markets are resident; a request that can never
+ * fit is refused at submission with IPFP_EBUDGET. An admitted market is
+ * packed on one of `lanes` HIP streams chosen by its size N*M, and each lane
+ * advances all of its resident markets together: every kernel of a sweep is
+ * one grouped launch over the lane's markets, `chunk` sweeps per scheduling
+ * round. Markets join and leave a lane at round boundaries. Each market keeps
+ * its own convergence state on the device and stops by itself (tol,
+ * max_sweeps), and its arithmetic -- splits, tiles, reduction order -- is the
+ * one ipfp_solve_market uses with the same options, so a request's (a, b) are
+ * bitwise identical to solving it alone.
+ *
+ * Ownership: the market's input buffers (factors, margins, b0) must stay
+ * valid, and its ipfp_result (with its device a, b and host res_hist) must
+ * stay allocated, until the request is reported finished. */
+typedef struct ipfp_server ipfp_server;
+
+typedef struct {
+  size_t arena_bytes;   /* device memory for resident markets; 0 = 1 GiB.
+                           Charged against the context's budget.            */
+  int32_t max_active;   /* resident markets at once, 1..1024; 0 = 256       */
+  int32_t lanes;        /* concurrent streams, 1..4; 0 = 3                  */
+  int32_t chunk;        /* sweeps per scheduling round, 1..64; 0 = 4        */
+  ipfp_dtype compute;   /* BF16 or FP8E4M3, for every request               */
+  int32_t tile_rows;    /* as ipfp_options.tile_rows, for every request     */
+  double lane_pairs[3]; /* rising upper bounds of N*M for lanes 0..lanes-2;
+                           0 = split log2(N*M) in [20, 36] evenly           */
+} ipfp_server_options;
+
+enum { IPFP_REQ_QUEUED = 0, IPFP_REQ_RUNNING = 1, IPFP_REQ_FINISHED = 2 };
+
+typedef struct {
+  int32_t state;        /* IPFP_REQ_*                                       */
+  int32_t code;         /* once finished: the solve's return code          */
+  int32_t lane;         /* lane the market runs on (-1 before admission)   */
+  double t_submit;      /* host CLOCK_MONOTONIC, milliseconds              */
+  double t_admit;       /* its set-up was enqueued                         */
+  double t_done;        /* its outputs were written                        */
+} ipfp_request_info;
+
+typedef struct {
+  int64_t submitted, admitted, finished, queued, active, rounds;
+  size_t arena_bytes, arena_used, arena_peak;
+  double pair_evals;    /* sum over finished requests of 2 N M sweeps      */
+} ipfp_server_stats;
+
+void ipfp_default_server_options(ipfp_server_options *opt);
+/* Allocates the arena and starts the scheduler thread. */
+int ipfp_server_create(ipfp_ctx *ctx, const ipfp_server_options *opt,
+                       ipfp_server **out);
+/* Cancels queued and running requests, waits for the scheduler to drain and
+ * frees the server. Tickets are invalid afterwards. */
+void ipfp_server_destroy(ipfp_server *srv);
+/* Queues a fused-path solve (validated as ipfp_solve_market; opt->compute
+ * must be the server's, opt->tile_rows 0 or the server's; use_graph and
+ * time_passes are ignored). The inputs are read after the work enqueued on
+ * `stream` so far has completed (an event is recorded there). Never blocks on
+ * the device. */
+int ipfp_submit(ipfp_server *srv, const ipfp_market *mk, const ipfp_options *opt,
+                ipfp_result *res, uint64_t *ticket, void *stream);
+/* IPFP_EBUSY while queued or running. Once finished: the request's return
+ * code (IPFP_OK, IPFP_NOT_CONVERGED, IPFP_ECANCELLED or an error), after
+ * which the ticket is forgotten (IPFP_ENOTFOUND). `info` may be NULL. */
+int ipfp_poll(ipfp_server *srv, uint64_t ticket, ipfp_request_info *info);
+/* As ipfp_poll, blocking up to timeout_ms (< 0: no limit). */
+int ipfp_wait(ipfp_server *srv, uint64_t ticket, double timeout_ms,
+              ipfp_request_info *info);
+/* A queued request finishes at once with IPFP_ECANCELLED; a running one at
+ * the end of its lane's round (its outputs are then not written). */
+int ipfp_cancel(ipfp_server *srv, uint64_t ticket);
+int ipfp_server_get_stats(ipfp_server *srv, ipfp_server_stats *out);
+/* The host clock the request times use (CLOCK_MONOTONIC), in ms. */
+double ipfp_clock_ms(void);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,8 @@ import dataclasses
 from . import _lib
 
 __all__ = ["IPFPError", "Context", "SolveInfo", "solve_market", "solve_market_phi",
-           "Market", "mu_pairs", "pack_side", "footprint", "library"]
+           "Market", "mu_pairs", "pack_side", "footprint", "library", "Server", "Request",
+           "clock_ms"]
 
 _DT = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "fp8": _lib.FP8E4M3,
        "fp8e4m3": _lib.FP8E4M3}
@@ -349,3 +350,140 @@ def footprint(N, M, d, path="fused", compute=None, splits=0, tile_rows=0) -> int
     _check(library().ipfp_footprint(ctypes.byref(mk), ctypes.byref(opt), ctypes.byref(out)),
            "ipfp_footprint")
     return out.value
+
+
+def clock_ms() -> float:
+    """The host clock (CLOCK_MONOTONIC, ms) that request times are taken on."""
+    return library().ipfp_clock_ms()
+
+
+@dataclasses.dataclass
+class Request:
+    """A submitted market: its outputs (filled once finished) and times."""
+    ticket: int
+    a: object
+    b: object
+    N: int
+    M: int
+    status: int = _lib.EBUSY
+    state: int = _lib.REQ_QUEUED
+    lane: int = -1
+    t_submit: float = 0.0
+    t_admit: float = 0.0
+    t_done: float = 0.0
+    info: SolveInfo = None
+
+    @property
+    def finished(self) -> bool:
+        return self.state == _lib.REQ_FINISHED
+
+
+class Server:
+    """Continuous-batching server (``ipfp_server_*``): submit markets, poll or
+    wait for them; the library's scheduler thread packs, groups and sweeps
+    them on the device."""
+
+    def __init__(self, arena_bytes=1 << 30, max_active=256, lanes=3, chunk=4,
+                 compute="bf16", tile_rows=0, lane_pairs=(0.0, 0.0, 0.0), ctx=None,
+                 device=0):
+        o = _lib.ServerOptions()
+        library().ipfp_default_server_options(ctypes.byref(o))
+        o.arena_bytes = int(arena_bytes)
+        o.max_active = int(max_active)
+        o.lanes = int(lanes)
+        o.chunk = int(chunk)
+        o.compute = _DT[compute]
+        o.tile_rows = int(tile_rows)
+        for k, v in enumerate(lane_pairs):
+            o.lane_pairs[k] = float(v)
+        self.compute = compute
+        self.ctx = ctx or Context.default(device)
+        h = ctypes.c_void_p()
+        _check(library().ipfp_server_create(self.ctx.handle, ctypes.byref(o),
+                                            ctypes.byref(h)), "ipfp_server_create")
+        self.handle = h
+        self._live = {}     # ticket -> (request, buffers the library uses)
+
+    def submit(self, U, Q, V, P, n, m, sigma, tol=1e-6, max_sweeps=100, check_every=1,
+               splits=0, b0=None, stream=None) -> Request:
+        torch = _torch()
+        mk = _market_struct(U, Q, V, P, n, m, sigma)
+        opt = _options("fused", self.compute, tol, max_sweeps, check_every, splits, 0, b0,
+                       False, False)
+        a = torch.empty(mk.N, dtype=torch.float64, device=U.device)
+        b = torch.empty(mk.M, dtype=torch.float64, device=U.device)
+        hist = (ctypes.c_double * 4096)()
+        r = _lib.Result()
+        r.a, r.b = a.data_ptr(), b.data_ptr()
+        r.res_hist = hist
+        r.res_cap = 4096
+        t = ctypes.c_uint64()
+        _check(library().ipfp_submit(self.handle, ctypes.byref(mk), ctypes.byref(opt),
+                                     ctypes.byref(r), ctypes.byref(t), _stream_ptr(stream)),
+               "ipfp_submit")
+        req = Request(t.value, a, b, mk.N, mk.M)
+        self._live[t.value] = (req, (U, Q, V, P, n, m, b0, mk, opt, r, hist))
+        return req
+
+    def _update(self, req, code, info):
+        req.state = info.state
+        req.lane = info.lane
+        req.t_submit, req.t_admit, req.t_done = info.t_submit, info.t_admit, info.t_done
+        if info.state == _lib.REQ_FINISHED:
+            _, keep = self._live.pop(req.ticket)
+            req.status = code
+            req.info = _info(code, keep[9], keep[10])
+
+    def poll(self, req: Request) -> bool:
+        if req.finished:
+            return True
+        info = _lib.RequestInfo()
+        code = library().ipfp_poll(self.handle, req.ticket, ctypes.byref(info))
+        if code == _lib.ENOTFOUND:
+            raise IPFPError(code, "ipfp_poll")
+        self._update(req, code, info)
+        return req.finished
+
+    def wait(self, req: Request, timeout_ms: float = -1.0) -> Request:
+        if req.finished:
+            return req
+        info = _lib.RequestInfo()
+        code = library().ipfp_wait(self.handle, req.ticket, float(timeout_ms),
+                                   ctypes.byref(info))
+        if code == _lib.ENOTFOUND:
+            raise IPFPError(code, "ipfp_wait")
+        self._update(req, code, info)
+        return req
+
+    def cancel(self, req: Request) -> None:
+        if not req.finished:
+            code = library().ipfp_cancel(self.handle, req.ticket)
+            if code not in (_lib.OK, _lib.EINVAL):
+                raise IPFPError(code, "ipfp_cancel")
+
+    def stats(self) -> dict:
+        st = _lib.ServerStats()
+        _check(library().ipfp_server_get_stats(self.handle, ctypes.byref(st)),
+               "ipfp_server_get_stats")
+        return {k: getattr(st, k) for k, _ in _lib.ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            library().ipfp_server_destroy(self.handle)
+            self.handle = None
+            for req, _ in list(self._live.values()):
+                req.state = _lib.REQ_FINISHED
+                req.status = _lib.ECANCELLED
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

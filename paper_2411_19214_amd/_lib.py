@@ -50,6 +50,35 @@ class Result(ctypes.Structure):
     ]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [
+        ("arena_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
+        ("lanes", ctypes.c_int32), ("chunk", ctypes.c_int32), ("compute", ctypes.c_int),
+        ("tile_rows", ctypes.c_int32), ("lane_pairs", ctypes.c_double * 3),
+    ]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_FINISHED = 0, 1, 2
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_int32), ("code", ctypes.c_int32), ("lane", ctypes.c_int32),
+        ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+        ("finished", ctypes.c_int64), ("queued", ctypes.c_int64),
+        ("active", ctypes.c_int64), ("rounds", ctypes.c_int64),
+        ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t),
+        ("arena_peak", ctypes.c_size_t), ("pair_evals", ctypes.c_double),
+    ]
+
+
 # name -> (restype, argtypes); every symbol the header declares
 SIGNATURES = {
     "ipfp_abi_version": (ctypes.c_int, []),
@@ -83,6 +112,20 @@ SIGNATURES = {
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "ipfp_default_server_options": (None, [ctypes.POINTER(ServerOptions)]),
+    "ipfp_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerOptions),
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "ipfp_server_destroy": (None, [ctypes.c_void_p]),
+    "ipfp_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Market),
+                                   ctypes.POINTER(Options), ctypes.POINTER(Result),
+                                   ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]),
+    "ipfp_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                 ctypes.POINTER(RequestInfo)]),
+    "ipfp_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double,
+                                 ctypes.POINTER(RequestInfo)]),
+    "ipfp_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ipfp_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "ipfp_clock_ms": (ctypes.c_double, []),
 }
 
 _LIB = None

@@ -140,6 +140,53 @@ hipError_t launch_fused_fixup(const FusedPass& fp, double* w2, int dbuf,
                               double* res_slot, Ctl* ctl, hipStream_t s);
 hipError_t launch_init_exp(const double* w, int64_t len, Ctl* ctl, int idx,
                            hipStream_t s);
+
+// ---- grouped launches (many resident markets per kernel launch) -------------
+
+// One market's half-sweep as the grouped pass, combine and fixup kernels read
+// it: the arguments of the single-market kernels, gathered in device memory.
+struct GroupHalf {
+  const uint8_t* Xo;        // output side operands (rows R)
+  const float* xscale;
+  const uint8_t* Yr;        // reduced side operands (rows L)
+  const float* yscale;
+  const double* wred;       // reduced side scaling (double-buffered if red_dbuf)
+  const float* shift;       // R fixed row shifts
+  double* part;             // nsplit x R partial sums
+  Ctl* ctl;
+  const double* marg;       // R margins
+  double* w2;               // output side scaling (double-buffered if dbuf)
+  double* res_block;        // combine blocks' residual maxima
+  double* res_slot;         // fixup blocks' residual maxima
+  int32_t* fix_list;
+  int32_t red_dbuf, exp_red, exp_out, R, L, tiles_per_split, nsplit, dbuf, residual,
+      kpad;
+};
+
+// One market's convergence check.
+struct GroupCheck {
+  Ctl* ctl;
+  const double* res_block;
+  double* hist;
+  int32_t nblocks;
+  SweepParams sp;
+};
+
+// Pass over markets idx[0..count) of table g; market idx[j] owns grid blocks
+// [first[j], first[j+1]), first[count] = total. All share kpad and waves.
+hipError_t launch_group_pass(const GroupHalf* g, const int32_t* idx, const int32_t* first,
+                             int count, int total, int64_t kpad, ipfp_dtype compute,
+                             int tile_rows, hipStream_t s);
+// Combine over markets 0..count of g with block ranges first[] (256 rows each).
+hipError_t launch_group_combine(const GroupHalf* g, const int32_t* first, int count,
+                                int total, hipStream_t s);
+// Fixup with `per` blocks per market.
+hipError_t launch_group_fixup(const GroupHalf* g, int count, int per, ipfp_dtype compute,
+                              hipStream_t s);
+hipError_t launch_group_check(const GroupCheck* c, int count, hipStream_t s);
+// Grid size and split bookkeeping of a single-market pass (what the grouped
+// pass must reproduce for bitwise-identical results).
+void fused_pass_grid(const FusedPass& fp, int64_t* blocks, int* tiles_per_split);
 int fused_auto_splits(int64_t R, int64_t L, int rows_per_wg);
 int fused_rows_per_wg(int64_t kpad, ipfp_dtype compute, int tile_rows);
 int fused_fixup_blocks();

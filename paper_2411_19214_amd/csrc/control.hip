@@ -11,9 +11,8 @@ namespace ipfp {
 // The residual of state i is available here because the row pass of sweep
 // i + 1 computes K v^(i) anyway; u^(i) is kept in the other half of a double
 // buffer, so stopping at i returns exactly (u^(i), v^(i)).
-__global__ void __launch_bounds__(256) k_check(Ctl* ctl, const double* res_block,
-                                               int nblocks, double* hist,
-                                               SweepParams sp) {
+__device__ __forceinline__ void check_body(Ctl* ctl, const double* res_block, int nblocks,
+                                           double* hist, const SweepParams& sp) {
   __shared__ double red[256];
   if (ctl->done) return;
   const int i = ctl->sweep;
@@ -54,6 +53,24 @@ __global__ void __launch_bounds__(256) k_check(Ctl* ctl, const double* res_block
     }
   }
   ctl->sweep = i + 1;
+}
+
+__global__ void __launch_bounds__(256) k_check(Ctl* ctl, const double* res_block,
+                                               int nblocks, double* hist,
+                                               SweepParams sp) {
+  check_body(ctl, res_block, nblocks, hist, sp);
+}
+
+// One workgroup per market.
+__global__ void __launch_bounds__(256) k_group_check(const GroupCheck* __restrict__ c) {
+  const GroupCheck& g = c[blockIdx.x];
+  check_body(g.ctl, g.res_block, g.nblocks, g.hist, g.sp);
+}
+
+hipError_t launch_group_check(const GroupCheck* c, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_group_check, dim3((unsigned)count), dim3(256), 0, s, c);
+  return hipGetLastError();
 }
 
 hipError_t launch_check(Ctl* ctl, const double* res_block, int nblocks,

@@ -228,19 +228,24 @@ __device__ __forceinline__ floatx16 mfma_step(const Frag& a, const Frag& b, floa
 // The reduction pass. MAXMODE: per (split, row) maximum of T over the split
 // (set-up). Otherwise the weighted sum S described at the top of this file.
 //
-// Sum mode runs two independent accumulators ("chains") at a time -- the two
-// output tiles of a wave (XT = 2) or two consecutive reduced subtiles (XT =
-// 1) -- so consecutive MFMAs never wait on each other, and the exp2/FMA
-// epilogue of the previous pair is spread between this pair's MFMAs: the
-// matrix cores and the transcendental/FMA pipe then work at the same time.
+// Where the MFMAs dominate a step (FP8 operands, BF16 with 2d = 128) sum mode
+// runs two independent accumulators ("chains") at a time -- the two output
+// tiles of a wave (XT = 2) or two consecutive reduced subtiles (XT = 1) -- so
+// consecutive MFMAs never wait on each other, and the exp2/FMA epilogue of the
+// previous pair is spread between this pair's MFMAs: the matrix cores and the
+// transcendental/FMA pipe then work at the same time. Elsewhere it finishes
+// one accumulator (MFMAs, then its epilogue) before the next.
+//
+// `bid` is the workgroup's index within this market's grid (blockIdx.x for a
+// single-market launch, the offset within the market's range of a grouped
+// launch).
 template <int KP, int XT, int WAVES, bool FP8, bool MAXMODE>
-__global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
-    k_fused_pass(const uint8_t* __restrict__ Xo, const float* __restrict__ xscale,
-                 const uint8_t* __restrict__ Yr, const float* __restrict__ yscale,
-                 const double* __restrict__ wred, int red_dbuf, int exp_red,
-                 int exp_out, const float* __restrict__ shift, int R, int L,
-                 int tiles_per_split, int nsplit, double* __restrict__ part,
-                 Ctl* ctl) {
+__device__ __forceinline__ void fused_pass_body(
+    const uint8_t* __restrict__ Xo, const float* __restrict__ xscale,
+    const uint8_t* __restrict__ Yr, const float* __restrict__ yscale,
+    const double* __restrict__ wred, int red_dbuf, int exp_red, int exp_out,
+    const float* __restrict__ shift, int R, int L, int tiles_per_split, int nsplit,
+    double* __restrict__ part, Ctl* ctl, const int bid) {
   typedef PassCore<KP, XT, WAVES, FP8> C;
   typedef typename C::Frag Frag;
   typedef Op<FP8> O;
@@ -256,7 +261,7 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
   __shared__ int32_t ysc[2][kTY];          // FP8: E8M0 scale byte per row
 
   if (ctl->done) return;
-  if (!MAXMODE && blockIdx.x == 0 && threadIdx.x == 0) {
+  if (!MAXMODE && bid == 0 && threadIdx.x == 0) {
     ctl->fix_rows = 0;
     ctl->wexp[exp_out] = INT_MIN;          // the combine of this pass sets it
   }
@@ -268,8 +273,8 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
-  const int split = blockIdx.x % nsplit;
-  const int rb = blockIdx.x / nsplit;
+  const int split = bid % nsplit;
+  const int rb = bid / nsplit;
   const int T = (L + kTY - 1) / kTY;
   const int t0 = split * tiles_per_split;
   const int t1 = min(T, t0 + tiles_per_split);
@@ -502,6 +507,45 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
   }
 }
 
+template <int KP, int XT, int WAVES, bool FP8, bool MAXMODE>
+__global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
+    k_fused_pass(const uint8_t* __restrict__ Xo, const float* __restrict__ xscale,
+                 const uint8_t* __restrict__ Yr, const float* __restrict__ yscale,
+                 const double* __restrict__ wred, int red_dbuf, int exp_red,
+                 int exp_out, const float* __restrict__ shift, int R, int L,
+                 int tiles_per_split, int nsplit, double* __restrict__ part,
+                 Ctl* ctl) {
+  fused_pass_body<KP, XT, WAVES, FP8, MAXMODE>(Xo, xscale, Yr, yscale, wred, red_dbuf,
+                                               exp_red, exp_out, shift, R, L,
+                                               tiles_per_split, nsplit, part, ctl,
+                                               (int)blockIdx.x);
+}
+
+// Grouped launch: the grid is the concatenation of several markets' grids;
+// market idx[j] owns blocks [first[j], first[j + 1]).
+__device__ __forceinline__ int group_find(const int32_t* __restrict__ first, int count,
+                                          int b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (__builtin_amdgcn_readfirstlane(first[mid]) <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int KP, int XT, int WAVES, bool FP8>
+__global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
+    k_group_pass(const GroupHalf* __restrict__ g, const int32_t* __restrict__ idx,
+                 const int32_t* __restrict__ first, int count) {
+  const int j = group_find(first, count, (int)blockIdx.x);
+  const GroupHalf& p = g[__builtin_amdgcn_readfirstlane(idx[j])];
+  fused_pass_body<KP, XT, WAVES, FP8, false>(
+      p.Xo, p.xscale, p.Yr, p.yscale, p.wred, p.red_dbuf, p.exp_red, p.exp_out, p.shift,
+      p.R, p.L, p.tiles_per_split, p.nsplit, p.part, p.ctl,
+      (int)blockIdx.x - __builtin_amdgcn_readfirstlane(first[j]));
+}
+
 // ---- combine partial sums, update scalings -----------------------------------
 
 // Finishes output row o given lS = log2((K w)_o): the residual of the current
@@ -543,18 +587,17 @@ __device__ __forceinline__ void block_finish(double res, int ex, double* res_slo
   }
 }
 
-__global__ void __launch_bounds__(256)
-    k_fused_combine(const double* __restrict__ part, int splits, int64_t R,
-                    const float* __restrict__ shift, int exp_red, int exp_out,
-                    const double* __restrict__ marg, double* w2, int dbuf,
-                    double* res_block, int32_t* fix_list, int residual, Ctl* ctl) {
+__device__ __forceinline__ void combine_body(
+    const double* __restrict__ part, int splits, int64_t R, const float* __restrict__ shift,
+    int exp_red, int exp_out, const double* __restrict__ marg, double* w2, int dbuf,
+    double* res_block, int32_t* fix_list, int residual, Ctl* ctl, const int bid) {
   if (ctl->done) return;
   const int i = ctl->sweep;
   const double* w_old = dbuf ? w2 + (int64_t)(i & 1) * R : w2;
   double* w_new = dbuf ? w2 + (int64_t)((i + 1) & 1) * R : w2;
   int E = ctl->wexp[exp_red];
   if (E == INT_MIN) E = 0;
-  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t o = (int64_t)bid * 256 + threadIdx.x;
   double res = 0.0;
   int ex = INT_MIN;
   if (o < R) {
@@ -569,7 +612,26 @@ __global__ void __launch_bounds__(256)
       ex = exponent_of(w_new[o]);
     }
   }
-  block_finish(res, ex, &res_block[blockIdx.x], &ctl->wexp[exp_out]);
+  block_finish(res, ex, &res_block[bid], &ctl->wexp[exp_out]);
+}
+
+__global__ void __launch_bounds__(256)
+    k_fused_combine(const double* __restrict__ part, int splits, int64_t R,
+                    const float* __restrict__ shift, int exp_red, int exp_out,
+                    const double* __restrict__ marg, double* w2, int dbuf,
+                    double* res_block, int32_t* fix_list, int residual, Ctl* ctl) {
+  combine_body(part, splits, R, shift, exp_red, exp_out, marg, w2, dbuf, res_block,
+               fix_list, residual, ctl, (int)blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256)
+    k_group_combine(const GroupHalf* __restrict__ g, const int32_t* __restrict__ first,
+                    int count) {
+  const int j = group_find(first, count, (int)blockIdx.x);
+  const GroupHalf& p = g[j];
+  combine_body(p.part, p.nsplit, p.R, p.shift, p.exp_red, p.exp_out, p.marg, p.w2, p.dbuf,
+               p.res_block, p.fix_list, p.residual, p.ctl,
+               (int)blockIdx.x - __builtin_amdgcn_readfirstlane(first[j]));
 }
 
 // The max pass's combine: h_o = -max over splits.
@@ -603,16 +665,15 @@ __device__ __forceinline__ float dot_packed(const uint8_t* a, const uint8_t* b,
 }
 
 template <bool FP8>
-__global__ void __launch_bounds__(256)
-    k_fused_fixup(const uint8_t* Xo, const float* xscale, const uint8_t* Yr,
-                  const float* yscale, int kpad, const double* wred, int red_dbuf,
-                  int exp_out, int64_t L, int64_t R, const double* marg, double* w2, int dbuf,
-                  double* res_slot, const int32_t* fix_list, int residual,
-                  Ctl* ctl) {
+__device__ __forceinline__ void fixup_body(
+    const uint8_t* Xo, const float* xscale, const uint8_t* Yr, const float* yscale, int kpad,
+    const double* wred, int red_dbuf, int exp_out, int64_t L, int64_t R, const double* marg,
+    double* w2, int dbuf, double* res_slot, const int32_t* fix_list, int residual, Ctl* ctl,
+    const int bid, const int nblocks) {
   __shared__ double dred[4];
   if (ctl->done) return;
   const int count = ctl->fix_rows;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->fix_total += count;
+  if (bid == 0 && threadIdx.x == 0) ctl->fix_total += count;
   const int i = ctl->sweep;
   const double* w_old = dbuf ? w2 + (int64_t)(i & 1) * R : w2;
   double* w_new = dbuf ? w2 + (int64_t)((i + 1) & 1) * R : w2;
@@ -620,7 +681,7 @@ __global__ void __launch_bounds__(256)
   const int ES = FP8 ? 1 : 2;
   double res = 0.0;
   int ex = INT_MIN;
-  for (int k = blockIdx.x; k < count; k += gridDim.x) {
+  for (int k = bid; k < count; k += nblocks) {
     const int64_t o = fix_list[k];
     const uint8_t* xr = Xo + o * kpad * ES;
     const float sx = FP8 ? xscale[o] : 1.f;
@@ -656,7 +717,30 @@ __global__ void __launch_bounds__(256)
       ex = max(ex, exponent_of(w_new[o]));
     }
   }
-  block_finish(res, ex, &res_slot[blockIdx.x], &ctl->wexp[exp_out]);
+  block_finish(res, ex, &res_slot[bid], &ctl->wexp[exp_out]);
+}
+
+template <bool FP8>
+__global__ void __launch_bounds__(256)
+    k_fused_fixup(const uint8_t* Xo, const float* xscale, const uint8_t* Yr,
+                  const float* yscale, int kpad, const double* wred, int red_dbuf,
+                  int exp_out, int64_t L, int64_t R, const double* marg, double* w2, int dbuf,
+                  double* res_slot, const int32_t* fix_list, int residual,
+                  Ctl* ctl) {
+  fixup_body<FP8>(Xo, xscale, Yr, yscale, kpad, wred, red_dbuf, exp_out, L, R, marg, w2,
+                  dbuf, res_slot, fix_list, residual, ctl, (int)blockIdx.x,
+                  (int)gridDim.x);
+}
+
+// Grouped fixup: `per` blocks per market, market j owns blocks [j per, (j+1) per).
+template <bool FP8>
+__global__ void __launch_bounds__(256)
+    k_group_fixup(const GroupHalf* __restrict__ g, int per) {
+  const int j = (int)blockIdx.x / per;
+  const GroupHalf& p = g[j];
+  fixup_body<FP8>(p.Xo, p.xscale, p.Yr, p.yscale, p.kpad, p.wred, p.red_dbuf, p.exp_out,
+                  p.L, p.R, p.marg, p.w2, p.dbuf, p.res_slot, p.fix_list, p.residual, p.ctl,
+                  (int)blockIdx.x - j * per, per);
 }
 
 // ctl->wexp[idx] = largest binary exponent of w (one workgroup).
@@ -778,6 +862,77 @@ hipError_t launch_fused_fixup(const FusedPass& fp, double* w2, int dbuf,
                        (const uint8_t*)fp.red.ops, fp.red.scale, (int)fp.kpad,
                        fp.w_red, fp.red_dbuf, fp.exp_out, fp.red.rows, fp.out.rows, fp.marg, w2,
                        dbuf, res_slot, fp.fix_list, fp.residual ? 1 : 0, ctl);
+  return hipGetLastError();
+}
+
+// ---- grouped dispatch -----------------------------------------------------------
+
+void fused_pass_grid(const FusedPass& fp, int64_t* blocks, int* tiles_per_split) {
+  const bool fp8 = fp.compute == IPFP_FP8E4M3;
+  const int rows_per_wg = fused_rows_per_wg(fp.kpad, fp.compute, fp.tile_rows);
+  const int ty = ty_for((int)fp.kpad * (fp8 ? 1 : 2));
+  const int64_t rblocks = (fp.out.rows + rows_per_wg - 1) / rows_per_wg;
+  const int T = (int)((fp.red.rows + ty - 1) / ty);
+  *tiles_per_split = (T + fp.splits - 1) / fp.splits;
+  *blocks = rblocks * fp.splits;
+}
+
+template <int KP, bool FP8>
+static hipError_t group_pass_kp(const GroupHalf* g, const int32_t* idx,
+                                const int32_t* first, int count, int total, int tile_rows,
+                                hipStream_t s) {
+  constexpr int XT = xt_for(KP, FP8);
+  if (tile_rows >= XT * 256)
+    hipLaunchKernelGGL((k_group_pass<KP, XT, 8, FP8>), dim3((unsigned)total), dim3(8 * 64),
+                       0, s, g, idx, first, count);
+  else
+    hipLaunchKernelGGL((k_group_pass<KP, XT, 4, FP8>), dim3((unsigned)total), dim3(4 * 64),
+                       0, s, g, idx, first, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_pass(const GroupHalf* g, const int32_t* idx, const int32_t* first,
+                             int count, int total, int64_t kpad, ipfp_dtype compute,
+                             int tile_rows, hipStream_t s) {
+  if (count <= 0 || total <= 0) return hipSuccess;
+  if (compute == IPFP_FP8E4M3) {
+    switch (kpad) {
+      case 64: return group_pass_kp<64, true>(g, idx, first, count, total, tile_rows, s);
+      case 128: return group_pass_kp<128, true>(g, idx, first, count, total, tile_rows, s);
+      case 192: return group_pass_kp<192, true>(g, idx, first, count, total, tile_rows, s);
+      case 256: return group_pass_kp<256, true>(g, idx, first, count, total, tile_rows, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (kpad) {
+    case 32: return group_pass_kp<32, false>(g, idx, first, count, total, tile_rows, s);
+    case 64: return group_pass_kp<64, false>(g, idx, first, count, total, tile_rows, s);
+    case 96: return group_pass_kp<96, false>(g, idx, first, count, total, tile_rows, s);
+    case 128: return group_pass_kp<128, false>(g, idx, first, count, total, tile_rows, s);
+    case 160: return group_pass_kp<160, false>(g, idx, first, count, total, tile_rows, s);
+    case 192: return group_pass_kp<192, false>(g, idx, first, count, total, tile_rows, s);
+    case 224: return group_pass_kp<224, false>(g, idx, first, count, total, tile_rows, s);
+    case 256: return group_pass_kp<256, false>(g, idx, first, count, total, tile_rows, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_group_combine(const GroupHalf* g, const int32_t* first, int count,
+                                int total, hipStream_t s) {
+  if (count <= 0 || total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_group_combine, dim3((unsigned)total), dim3(256), 0, s, g, first,
+                     count);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_fixup(const GroupHalf* g, int count, int per, ipfp_dtype compute,
+                              hipStream_t s) {
+  if (count <= 0 || per <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)(count * per);
+  if (compute == IPFP_FP8E4M3)
+    hipLaunchKernelGGL(k_group_fixup<true>, dim3(grid), dim3(256), 0, s, g, per);
+  else
+    hipLaunchKernelGGL(k_group_fixup<false>, dim3(grid), dim3(256), 0, s, g, per);
   return hipGetLastError();
 }
 

@@ -7,11 +7,8 @@
 #include <string.h>
 
 #include <algorithm>
-#include <chrono>
-#include <mutex>
-#include <vector>
 
-#include "common.h"
+#include "handle.h"
 
 using namespace ipfp;
 
@@ -21,100 +18,12 @@ using namespace ipfp;
     if (e_ != hipSuccess) return IPFP_EHIP;  \
   } while (0)
 
-struct ipfp_ctx {
-  int device;
-  size_t budget;
-  size_t used;
-  std::mutex mu;
-};
-
-namespace {
-
-constexpr int kHistCap = 4096;  // device residual history entries per market
-
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-// Carves one device allocation into aligned sub-buffers.
-struct Carver {
-  size_t off = 0;
-  char* base = nullptr;
-  template <typename T>
-  T* take(size_t count) {
-    off = align_up(off, 256);
-    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off += count * sizeof(T);
-    return p;
-  }
-};
-
-size_t dtype_size(ipfp_dtype t) {
-  switch (t) {
-    case IPFP_F64: return 8;
-    case IPFP_F32: return 4;
-    case IPFP_BF16: return 2;
-    default: return 1;
-  }
-}
-
-double now_ms() {
-  return std::chrono::duration<double, std::milli>(
-             std::chrono::steady_clock::now().time_since_epoch())
-      .count();
-}
-
-}  // namespace
-
-struct ipfp_handle {
-  ipfp_ctx* ctx = nullptr;
-  ipfp_market mk{};
-  ipfp_options opt{};
-  bool plain = false;
-  int64_t N = 0, M = 0;
-  size_t bytes = 0;
-  char* mem = nullptr;
-  // shared state
-  Ctl* ctl = nullptr;
-  double* hist = nullptr;
-  double* res_block = nullptr;   // row residual maxima (combine + fixup slots)
-  double* res_dummy = nullptr;   // column side writes its (unused) maxima here
-  double* u2 = nullptr;          // 2 x N double buffer
-  double* v = nullptr;           // M
-  int nres_row = 0;              // entries of res_block the check reduces
-  // plain path
-  ipfp_dtype kdt = IPFP_F32;
-  void* K = nullptr;
-  int64_t ldk = 0;
-  double* cshift = nullptr;
-  double* ut = nullptr;
-  double* part = nullptr;
-  int psplits = 1;
-  // fused path
-  int64_t kpad = 0;
-  void *xop = nullptr, *yop = nullptr;
-  float *xscale = nullptr, *yscale = nullptr;
-  float *xshift = nullptr, *yshift = nullptr;
-  double *xpart = nullptr, *ypart = nullptr;
-  int32_t *xfix = nullptr, *yfix = nullptr;
-  FusedPass rowp{}, colp{};
-  int row_combine_blocks = 0, col_combine_blocks = 0;
-  // loop state
-  int units = 0;                 // sweep units enqueued so far
-  Ctl* host_ctl = nullptr;       // pinned mirror
-  hipGraphExec_t graph = nullptr;
-  int graph_units = 0;
-  hipStream_t cap_stream = nullptr;
-  std::vector<hipEvent_t> evs;   // pass timing events (pairs)
-  double pass_ms = 0.0;
-  int pass_launches = 0;
-  double loop_ms = 0.0;
-  double setup_ms = 0.0;
-};
-
 // ---- sizes -------------------------------------------------------------------
 
-static void layout(ipfp_handle* h, Carver& cv) {
+void ipfp::handle_layout(ipfp_handle* h, Carver& cv) {
   const int64_t N = h->N, M = h->M;
   h->ctl = cv.take<Ctl>(1);
+  if (h->ext_ctl) h->ctl = h->ext_ctl;
   h->hist = cv.take<double>(kHistCap);
   h->u2 = cv.take<double>(2 * N);
   h->v = cv.take<double>(M);
@@ -158,7 +67,7 @@ static void layout(ipfp_handle* h, Carver& cv) {
   }
 }
 
-static int validate(const ipfp_market* mk, const ipfp_options* opt, bool factors) {
+int ipfp::validate_market(const ipfp_market* mk, const ipfp_options* opt, bool factors) {
   if (!mk || !opt) return IPFP_EINVAL;
   if (mk->N < 1 || mk->M < 1) return IPFP_EINVAL;
   if (mk->N > INT32_MAX || mk->M > INT32_MAX) return IPFP_EINVAL;
@@ -191,7 +100,7 @@ static int validate(const ipfp_market* mk, const ipfp_options* opt, bool factors
 
 // ---- sweep units ---------------------------------------------------------------
 
-static SweepParams sweep_params(const ipfp_handle* h) {
+SweepParams ipfp::handle_sweep_params(const ipfp_handle* h) {
   SweepParams sp;
   sp.tol = h->opt.tol;
   sp.max_sweeps = h->opt.max_sweeps;
@@ -225,7 +134,7 @@ static hipError_t timed(ipfp_handle* h, bool timing, hipStream_t s, F&& fn) {
 // check, then the column half-sweep (skipped on the device once done).
 static hipError_t enqueue_unit(ipfp_handle* h, hipStream_t s, bool timing) {
   hipError_t e;
-  const SweepParams sp = sweep_params(h);
+  const SweepParams sp = handle_sweep_params(h);
   int nb = 0;
   if (h->plain) {
     e = timed(h, timing, s, [&] {
@@ -274,6 +183,68 @@ static void collect_events(ipfp_handle* h) {
     (void)hipEventDestroy(h->evs[k + 1]);
   }
   h->evs.clear();
+}
+
+int ipfp::ctx_reserve(ipfp_ctx* ctx, size_t bytes) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (ctx->budget && ctx->used + bytes > ctx->budget) return IPFP_EBUDGET;
+  ctx->used += bytes;
+  return IPFP_OK;
+}
+
+void ipfp::ctx_release(ipfp_ctx* ctx, size_t bytes) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->used -= bytes;
+}
+
+#define TRY(expr)                        \
+  do {                                   \
+    hipError_t e_ = (expr);              \
+    if (e_ != hipSuccess) return e_;     \
+  } while (0)
+
+hipError_t ipfp::handle_setup(ipfp_handle* h, const void* phi, ipfp_dtype phi_dt,
+                              int64_t ld_phi, hipStream_t s) {
+  const ipfp_market* mk = &h->mk;
+  const ipfp_options* opt = &h->opt;
+  TRY(hipMemsetAsync(h->ctl, 0, sizeof(Ctl), s));
+  TRY(launch_validate_margins(mk->n, h->N, mk->m, h->M, h->ctl, s));
+  TRY(launch_init_vec(h->u2, nullptr, 2 * h->N, s));
+  TRY(launch_init_vec(h->v, opt->b0, h->M, s));
+  if (h->plain) {
+    if (phi) {
+      return launch_materialize(phi, phi_dt, ld_phi, h->K, h->kdt, h->ldk, h->N, h->M,
+                                mk->sigma, h->cshift, h->ctl, s);
+    }
+    TRY(launch_phi_from_factors(mk->U, mk->Q, mk->V, mk->P, mk->in_dtype, mk->ld_x,
+                                mk->ld_y, h->N, h->M, mk->d, h->K, h->kdt, h->ldk, s));
+    return launch_materialize(h->K, h->kdt, h->ldk, h->K, h->kdt, h->ldk, h->N, h->M,
+                              mk->sigma, h->cshift, h->ctl, s);
+  }
+  const ipfp_dtype cd = opt->compute;
+  const float ps = fused_prescale(mk->sigma);
+  TRY(launch_pack(mk->U, mk->Q, mk->in_dtype, mk->ld_x, h->N, mk->d, cd, h->kpad, ps,
+                  h->xop, h->xscale, h->ctl, s));
+  TRY(launch_pack(mk->V, mk->P, mk->in_dtype, mk->ld_y, h->M, mk->d, cd, h->kpad, ps,
+                  h->yop, h->yscale, h->ctl, s));
+  FusedSide X{h->xop, cd == IPFP_FP8E4M3 ? h->xscale : nullptr, h->N};
+  FusedSide Y{h->yop, cd == IPFP_FP8E4M3 ? h->yscale : nullptr, h->M};
+  FusedPass& r = h->rowp;
+  r.out = X; r.red = Y; r.compute = cd; r.kpad = h->kpad;
+  r.w_red = h->v; r.red_dbuf = 0; r.exp_red = 1; r.exp_out = 0;
+  r.shift = h->xshift; r.marg = mk->n;
+  r.part = h->xpart; r.res_block = h->res_block; r.fix_list = h->xfix;
+  r.residual = true;
+  FusedPass& q = h->colp;
+  q.out = Y; q.red = X; q.compute = cd; q.kpad = h->kpad;
+  q.w_red = h->u2; q.red_dbuf = 1; q.exp_red = 0; q.exp_out = 1;
+  q.shift = h->yshift; q.marg = mk->m;
+  q.part = h->ypart; q.res_block = h->res_dummy; q.fix_list = h->yfix;
+  q.residual = false;
+  // fixed row shifts h = -max T from one max pass per side; exponent of v0
+  TRY(launch_fused_shift(r, h->ctl, s));
+  TRY(launch_fused_shift(q, h->ctl, s));
+  return launch_init_exp(h->v, h->M, h->ctl, 1, s);
 }
 
 // ---- C ABI -------------------------------------------------------------------
@@ -331,7 +302,7 @@ static int footprint_impl(const ipfp_market* mk, const ipfp_options* opt,
   h.M = mk->M;
   h.kdt = opt->compute == IPFP_F64 ? IPFP_F64 : IPFP_F32;
   Carver cv;
-  layout(&h, cv);
+  handle_layout(&h, cv);
   *bytes = align_up(cv.off, 256);
   return IPFP_OK;
 }
@@ -339,21 +310,9 @@ static int footprint_impl(const ipfp_market* mk, const ipfp_options* opt,
 int ipfp_footprint(const ipfp_market* mk, const ipfp_options* opt,
                    size_t* bytes_out) {
   if (!bytes_out) return IPFP_EINVAL;
-  int rc = validate(mk, opt, true);
+  int rc = validate_market(mk, opt, true);
   if (rc != IPFP_OK) return rc;
   return footprint_impl(mk, opt, opt->path == IPFP_PATH_PLAIN, bytes_out);
-}
-
-static int reserve(ipfp_ctx* ctx, size_t bytes) {
-  std::lock_guard<std::mutex> g(ctx->mu);
-  if (ctx->budget && ctx->used + bytes > ctx->budget) return IPFP_EBUDGET;
-  ctx->used += bytes;
-  return IPFP_OK;
-}
-
-static void release(ipfp_ctx* ctx, size_t bytes) {
-  std::lock_guard<std::mutex> g(ctx->mu);
-  ctx->used -= bytes;
 }
 
 static void destroy_handle(ipfp_handle* h) {
@@ -362,8 +321,10 @@ static void destroy_handle(ipfp_handle* h) {
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->host_ctl) (void)hipHostFree(h->host_ctl);
-  if (h->mem) (void)hipFree(h->mem);
-  if (h->ctx && h->bytes) release(h->ctx, h->bytes);
+  if (!h->arena) {
+    if (h->mem) (void)hipFree(h->mem);
+    if (h->ctx && h->bytes) ctx_release(h->ctx, h->bytes);
+  }
   delete h;
 }
 
@@ -383,9 +344,9 @@ static int open_impl(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* o
   h->M = mk->M;
   h->kdt = opt->compute == IPFP_F64 ? IPFP_F64 : IPFP_F32;
   Carver cv;
-  layout(h, cv);
+  handle_layout(h, cv);
   const size_t bytes = align_up(cv.off, 256);
-  int rc = reserve(ctx, bytes);
+  int rc = ctx_reserve(ctx, bytes);
   if (rc != IPFP_OK) {
     delete h;
     return rc;
@@ -403,59 +364,13 @@ static int open_impl(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* o
   }
   Carver real;
   real.base = h->mem;
-  layout(h, real);
+  handle_layout(h, real);
 
   auto fail = [&](int code) {
     destroy_handle(h);
     return code;
   };
-  if (hipMemsetAsync(h->ctl, 0, sizeof(Ctl), s) != hipSuccess) return fail(IPFP_EHIP);
-  if (launch_validate_margins(mk->n, h->N, mk->m, h->M, h->ctl, s) != hipSuccess)
-    return fail(IPFP_EHIP);
-  if (launch_init_vec(h->u2, nullptr, 2 * h->N, s) != hipSuccess) return fail(IPFP_EHIP);
-  if (launch_init_vec(h->v, opt->b0, h->M, s) != hipSuccess) return fail(IPFP_EHIP);
-
-  if (h->plain) {
-    hipError_t e;
-    if (phi) {
-      e = launch_materialize(phi, phi_dt, ld_phi, h->K, h->kdt, h->ldk, h->N, h->M,
-                             mk->sigma, h->cshift, h->ctl, s);
-    } else {
-      e = launch_phi_from_factors(mk->U, mk->Q, mk->V, mk->P, mk->in_dtype, mk->ld_x,
-                                  mk->ld_y, h->N, h->M, mk->d, h->K, h->kdt, h->ldk, s);
-      if (e == hipSuccess)
-        e = launch_materialize(h->K, h->kdt, h->ldk, h->K, h->kdt, h->ldk, h->N, h->M,
-                               mk->sigma, h->cshift, h->ctl, s);
-    }
-    if (e != hipSuccess) return fail(IPFP_EHIP);
-  } else {
-    const ipfp_dtype cd = opt->compute;
-    const float ps = fused_prescale(mk->sigma);
-    if (launch_pack(mk->U, mk->Q, mk->in_dtype, mk->ld_x, h->N, mk->d, cd, h->kpad, ps,
-                    h->xop, h->xscale, h->ctl, s) != hipSuccess ||
-        launch_pack(mk->V, mk->P, mk->in_dtype, mk->ld_y, h->M, mk->d, cd, h->kpad, ps,
-                    h->yop, h->yscale, h->ctl, s) != hipSuccess)
-      return fail(IPFP_EHIP);
-    FusedSide X{h->xop, cd == IPFP_FP8E4M3 ? h->xscale : nullptr, h->N};
-    FusedSide Y{h->yop, cd == IPFP_FP8E4M3 ? h->yscale : nullptr, h->M};
-    FusedPass& r = h->rowp;
-    r.out = X; r.red = Y; r.compute = cd; r.kpad = h->kpad;
-    r.w_red = h->v; r.red_dbuf = 0; r.exp_red = 1; r.exp_out = 0;
-    r.shift = h->xshift; r.marg = mk->n;
-    r.part = h->xpart; r.res_block = h->res_block; r.fix_list = h->xfix;
-    r.residual = true;
-    FusedPass& q = h->colp;
-    q.out = Y; q.red = X; q.compute = cd; q.kpad = h->kpad;
-    q.w_red = h->u2; q.red_dbuf = 1; q.exp_red = 0; q.exp_out = 1;
-    q.shift = h->yshift; q.marg = mk->m;
-    q.part = h->ypart; q.res_block = h->res_dummy; q.fix_list = h->yfix;
-    q.residual = false;
-    // fixed row shifts h = -max T from one max pass per side; exponent of v0
-    if (launch_fused_shift(r, h->ctl, s) != hipSuccess ||
-        launch_fused_shift(q, h->ctl, s) != hipSuccess ||
-        launch_init_exp(h->v, h->M, h->ctl, 1, s) != hipSuccess)
-      return fail(IPFP_EHIP);
-  }
+  if (handle_setup(h, phi, phi_dt, ld_phi, s) != hipSuccess) return fail(IPFP_EHIP);
   if (read_ctl(h, s) != IPFP_OK) return fail(IPFP_EHIP);
   if (h->host_ctl->bad_margin) return fail(IPFP_EINVAL);
   if (h->host_ctl->nonfinite) return fail(IPFP_ENONFINITE);
@@ -467,7 +382,7 @@ static int open_impl(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* o
 int ipfp_market_open(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* opt,
                      ipfp_handle** out, void* stream) {
   if (!ctx || !out) return IPFP_EINVAL;
-  int rc = validate(mk, opt, true);
+  int rc = validate_market(mk, opt, true);
   if (rc != IPFP_OK) return rc;
   return open_impl(ctx, mk, opt, nullptr, IPFP_F32, 0, out, (hipStream_t)stream);
 }
@@ -574,7 +489,7 @@ static int solve_handle(ipfp_handle* h, ipfp_result* res, hipStream_t s) {
 int ipfp_solve_market(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* opt,
                       ipfp_result* res, void* stream) {
   if (!ctx || !res || !res->a || !res->b) return IPFP_EINVAL;
-  int rc = validate(mk, opt, true);
+  int rc = validate_market(mk, opt, true);
   if (rc != IPFP_OK) return rc;
   ipfp_handle* h = nullptr;
   rc = open_impl(ctx, mk, opt, nullptr, IPFP_F32, 0, &h, (hipStream_t)stream);
@@ -601,7 +516,7 @@ int ipfp_solve_market_phi(ipfp_ctx* ctx, int64_t N, int64_t M, ipfp_dtype phi_dt
   ipfp_options o = *opt;
   o.path = IPFP_PATH_PLAIN;
   if (o.compute != IPFP_F64) o.compute = IPFP_F32;
-  int rc = validate(&mk, &o, false);
+  int rc = validate_market(&mk, &o, false);
   if (rc != IPFP_OK) return rc;
   ipfp_handle* h = nullptr;
   rc = open_impl(ctx, &mk, &o, Phi, phi_dtype, ld_phi, &h, (hipStream_t)stream);

@@ -1,0 +1,154 @@
+"""GPU tests of the serving layer: grouped launches over many resident markets
+must give every request exactly the result of solving it alone (the grouped
+kernels run the single-market arithmetic per market), small requests must
+match the FP64 oracle, and admission, cancellation and error reporting must
+behave as documented."""
+import numpy as np
+import pytest
+
+import workloads
+from helpers import banner, market_tensors, rel_err, require_gpu, to_dev
+from oracle import ipfp as O, quant
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2411_19214_amd as L
+    return L
+
+
+# (N, M, d, sigma, tol, max_sweeps, check_every): sizes across all three lanes,
+# ragged against every tile, two kpads (d = 32 -> 64, d = 40 -> 96)
+MIX = [
+    (700, 1300, 32, 1.0, 1e-6, 60, 1),
+    (1500, 900, 32, 0.5, 1e-6, 60, 1),
+    (3100, 2900, 32, 1.0, 0.0, 9, 3),
+    (5000, 7001, 40, 0.5, 1e-6, 60, 2),
+    (9000, 12000, 32, 1.0, 1e-6, 60, 1),
+    (12345, 9876, 40, 1.0, 1e-6, 60, 1),
+    (30000, 20000, 32, 0.5, 1e-6, 40, 4),
+    (70000, 60000, 32, 1.0, 1e-6, 30, 1),
+]
+
+
+def mix_market(i, N, M, d, sigma):
+    return workloads.factor_market(N, M, d, 1.0 / d, sigma, col_margin="uint1-5",
+                                   seed=19214 + 7000 + i, name=f"mix{i}")
+
+
+def alone(torch, lib, t, spec, compute):
+    N, M, d, sigma, tol, ms, ce = spec
+    return lib.solve_market(*t, sigma, tol=tol, max_sweeps=ms, check_every=ce,
+                            compute=compute)
+
+
+@pytest.mark.parametrize("compute", ["bf16", "fp8"])
+def test_mix_equals_alone_bitwise(torch, lib, compute):
+    banner(f"serve mix vs alone {compute}")
+    mks = [mix_market(i, *s[:4]) for i, s in enumerate(MIX)]
+    tens = [market_tensors(torch, mk) for mk in mks]
+    with lib.Server(compute=compute, chunk=3, lanes=3) as srv:
+        reqs = []
+        # half now, the rest while the first half runs
+        for i, (t, s) in enumerate(zip(tens, MIX)):
+            N, M, d, sigma, tol, ms, ce = s
+            reqs.append(srv.submit(*t, sigma, tol=tol, max_sweeps=ms, check_every=ce))
+            if i == len(MIX) // 2:
+                srv.wait(reqs[0])
+        for r in reqs:
+            srv.wait(r, timeout_ms=60_000)
+        lanes = {r.lane for r in reqs}
+        st = srv.stats()
+    assert all(r.finished for r in reqs)
+    assert len(lanes) == 3, lanes
+    assert st["finished"] == len(MIX) and st["arena_used"] == 0
+    for t, s, r in zip(tens, MIX, reqs):
+        a, b, info = alone(torch, lib, t, s, compute)
+        assert r.status == info.status, (s, r.status, info.status)
+        assert r.info.sweeps == info.sweeps and r.info.residuals == info.residuals, s
+        assert torch.equal(r.a, a) and torch.equal(r.b, b), s
+        assert r.t_submit <= r.t_admit <= r.t_done
+
+
+def test_small_requests_match_oracle(torch, lib):
+    banner("serve small requests vs oracle")
+    specs = MIX[:2]
+    mks = [mix_market(i, *s[:4]) for i, s in enumerate(specs)]
+    with lib.Server() as srv:
+        reqs = [srv.submit(*market_tensors(torch, mk), s[3], tol=s[4], max_sweeps=s[5],
+                           check_every=s[6]) for mk, s in zip(mks, specs)]
+        for r in reqs:
+            srv.wait(r)
+    for mk, s, r in zip(mks, specs, reqs):
+        X = quant.packed_rows(np.concatenate([mk.U, mk.Q], 1), mk.sigma, "bf16")
+        Y = quant.packed_rows(np.concatenate([mk.V, mk.P], 1), mk.sigma, "bf16")
+        ref = O.ipfp_batch(O.kernel_from_log2(X @ Y.T), mk.n, mk.m, tol=s[4],
+                           max_sweeps=s[5], check_every=s[6])
+        assert r.info.sweeps == ref.sweeps
+        assert rel_err(r.a.cpu().numpy(), ref.a) < 2e-5
+        assert rel_err(r.b.cpu().numpy(), ref.b) < 2e-5
+
+
+def test_admission_by_footprint(torch, lib):
+    banner("serve admission under a small arena")
+    specs = [MIX[4], MIX[5], MIX[4], MIX[5]]
+    foot = max(lib.footprint(s[0], s[1], s[2]) for s in specs)
+    mks = [mix_market(10 + i, *s[:4]) for i, s in enumerate(specs)]
+    tens = [market_tensors(torch, mk) for mk in mks]
+    with lib.Server(arena_bytes=int(foot * 2.2)) as srv:
+        reqs = [srv.submit(*t, s[3], tol=s[4], max_sweeps=s[5], check_every=s[6])
+                for t, s in zip(tens, specs)]
+        for r in reqs:
+            srv.wait(r)
+        st = srv.stats()
+        # a market that can never fit is refused at once
+        big = workloads.factor_market(200_000, 200_000, 32, 1 / 32, 1.0, seed=5, name="big")
+        with pytest.raises(lib.IPFPError) as e:
+            srv.submit(*market_tensors(torch, big), 1.0)
+        assert e.value.code == -2
+    assert st["arena_peak"] <= st["arena_bytes"]
+    # not all four fit at once, so someone waited for a slot
+    assert max(r.t_admit for r in reqs) >= min(r.t_done for r in reqs)
+    for t, s, r in zip(tens, specs, reqs):
+        a, b, info = alone(torch, lib, t, s, "bf16")
+        assert torch.equal(r.a, a) and torch.equal(r.b, b)
+
+
+def test_cancel_and_errors(torch, lib):
+    banner("serve cancel, invalid margin, compute mismatch")
+    s = MIX[6]
+    mk = mix_market(20, *s[:4])
+    t = market_tensors(torch, mk)
+    bad = mix_market(21, 900, 800, 32, 1.0)
+    U, Q, V, P, n, m = market_tensors(torch, bad)
+    m[5] = 0.0
+    with lib.Server(max_active=1) as srv:
+        long = srv.submit(*t, s[3], tol=0.0, max_sweeps=100_000)
+        queued = srv.submit(*t, s[3], tol=0.0, max_sweeps=10)
+        broken = srv.submit(U, Q, V, P, n, m, 1.0, tol=1e-6)
+        srv.cancel(queued)
+        srv.wait(queued)
+        assert queued.status == -5 and queued.t_admit == 0.0
+        srv.cancel(long)
+        srv.wait(long, timeout_ms=60_000)
+        assert long.status == -5
+        srv.wait(broken, timeout_ms=60_000)
+        assert broken.status == -1
+        # a request whose compute differs from the server's is refused
+        import ctypes
+        from paper_2411_19214_amd import _lib
+        mk_s = lib._market_struct(*t, s[3])
+        opt = lib._options("fused", "fp8", 1e-6, 10, 1, 0, 0, None, False, False)
+        res = _lib.Result()
+        res.a, res.b = long.a.data_ptr(), long.b.data_ptr()
+        tk = ctypes.c_uint64()
+        rc = lib.library().ipfp_submit(srv.handle, ctypes.byref(mk_s), ctypes.byref(opt),
+                                       ctypes.byref(res), ctypes.byref(tk), None)
+        assert rc == -1
