@@ -10,10 +10,11 @@ Default workload: the fused BF16 path on the N = M = 1,000,000, d = 64
 market (factors N(0, 1/64), sigma = 1, n = 1, m uniform on 1..10), with the
 factors resident in HBM before timing starts. The same JSON line also reports
 the plain FP32 (materialised K) and fused BF16 paths on the 20,000 x 20,000,
-d = 32 market at a fixed 500 sweeps, the roofline of the dominant kernel and
-the CPU oracle timed on a bounded sample of the default workload.
+d = 32 market at a fixed 500 sweeps, the serving mix (512 markets arriving
+at 200/s, p50/p99 solve latency), the roofline of the dominant kernel and the
+CPU oracle timed on a bounded sample of the default workload.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c2]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c2] [--no-serve]
 """
 from __future__ import annotations
 
@@ -118,6 +119,54 @@ def run_c2(torch, L, sweeps=500):
     return out
 
 
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else None
+
+
+def run_serving(torch, L, count=512, rate_hz=200.0):
+    """The serving mix: `count` markets (N, M log-uniform in [1e3, 2e5], d = 32,
+    sigma in {0.5, 1}, unit margins, tol 1e-6) submitted at Poisson(rate)
+    arrival times to one continuous-batching server; factors are generated on
+    the device before the clock starts."""
+    reqs = workloads.serving_requests(count=count, rate_hz=rate_hz)
+    log(f"serving: generating {count} markets on the device")
+    tens = [workloads.device_request_factors(torch, r) for r in reqs]
+    torch.cuda.synchronize()
+    with L.Server(arena_bytes=16 << 30, max_active=256, lanes=3, chunk=4) as srv:
+        # load the grouped kernels once, outside the measured window
+        w = srv.submit(*workloads.device_request_factors(
+            torch, workloads.Request(-1, 0.0, 1000, 1000, 32, 1.0, 1)), 1.0, tol=1e-6)
+        srv.wait(w)
+        log(f"serving: submitting at {rate_hz:.0f}/s")
+        handles = []
+        t0 = L.clock_ms()
+        for r, t in zip(reqs, tens):
+            due = t0 + 1e3 * r.arrival_s
+            while True:
+                now = L.clock_ms()
+                if now >= due:
+                    break
+                time.sleep(min(0.002, (due - now) / 1e3))
+            handles.append(srv.submit(*t, r.sigma, tol=1e-6, max_sweeps=200))
+        log("serving: all submitted, waiting")
+        for h in handles:
+            srv.wait(h)
+        st = srv.stats()
+    t_end = max(h.t_done for h in handles)
+    soj = [h.t_done - h.t_submit for h in handles]
+    svc = [h.t_done - h.t_admit for h in handles]
+    que = [h.t_admit - h.t_submit for h in handles]
+    pe = sum(2.0 * h.N * h.M * h.info.sweeps for h in handles)
+    ok = sum(1 for h in handles if h.status == 0)
+    return {"requests": count, "rate_hz": rate_hz, "converged": ok,
+            "sojourn_ms_p50": pct(soj, 50), "sojourn_ms_p99": pct(soj, 99),
+            "service_ms_p50": pct(svc, 50), "service_ms_p99": pct(svc, 99),
+            "queue_ms_p50": pct(que, 50), "queue_ms_p99": pct(que, 99),
+            "makespan_ms": t_end - t0, "pair_evals_per_s": pe / ((t_end - t0) / 1e3),
+            "mean_sweeps": float(np.mean([h.info.sweeps for h in handles])),
+            "rounds": st["rounds"], "arena_peak_bytes": st["arena_peak"]}
+
+
 def cpu_baseline(mk, budget_s=15.0):
     """The oracle's mini-batch half-step (FP64 GEMM + exp + matvec) on row
     blocks of the default workload, timed on the host until ~budget_s."""
@@ -148,6 +197,9 @@ def main():
     ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--size", type=int, default=1_000_000,
                     help="N = M of the default workload (1e6 unless testing)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving mix (testing)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -167,6 +219,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.serve_only:
+        print(json.dumps({"serving": run_serving(torch, L)}), flush=True)
+        return
     cfg = workloads.CONFIGS[3]
     log(f"generating C3 market N=M={args.size} d={cfg['d']}")
     mk = workloads.config_market(3, N=args.size, M=args.size)
@@ -210,6 +265,9 @@ def main():
     if not args.no_c2:
         log("C2: plain FP32 vs fused BF16, 500 sweeps")
         line["c2_20k"] = run_c2(torch, L)
+    if not args.no_serve:
+        log("serving mix: 512 markets, Poisson 200/s")
+        line["serving"] = run_serving(torch, L)
     if not args.no_cpu:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(mk)

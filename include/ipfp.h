@@ -218,14 +218,18 @@ int ipfp_pack_side(ipfp_ctx *ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
  *
  * The paper solves one market at a time; a server solves a stream of
  * independent markets (requests) concurrently on one device. It owns one slab
- * of device memory (its arena) and a scheduler thread. Requests are admitted
- * in submission order while their footprint (ipfp_footprint) fits the arena
- * and fewer than max_active markets are resident; a request that can never
- * fit is refused at submission with IPFP_EBUDGET. An admitted market is
- * packed on one of `lanes` HIP streams chosen by its size N*M, and each lane
- * advances all of its resident markets together: every kernel of a sweep is
- * one grouped launch over the lane's markets, `chunk` sweeps per scheduling
- * round. Markets join and leave a lane at round boundaries. Each market keeps
+ * of device memory (its arena) and a scheduler thread. Each request belongs
+ * to one of `lanes` HIP streams chosen by its size N*M. The scheduler admits
+ * queued requests smallest first, where a request's size counts as
+ * log2(N*M) minus its waiting time over aging_ms (so nothing waits forever),
+ * while its footprint (ipfp_footprint) fits the arena, fewer than max_active
+ * markets are resident and its lane holds fewer than lane_blocks reduction
+ * workgroups per pass (a lane with no market always takes one). A request
+ * that can never fit the arena is refused at submission with IPFP_EBUDGET.
+ * Each lane advances all of its resident markets together: every kernel of a
+ * sweep is one grouped launch over the lane's markets, `chunk` sweeps per
+ * scheduling round. Markets join and leave a lane at round boundaries. Each
+ * market keeps
  * its own convergence state on the device and stops by itself (tol,
  * max_sweeps), and its arithmetic -- splits, tiles, reduction order -- is the
  * one ipfp_solve_market uses with the same options, so a request's (a, b) are
@@ -246,6 +250,9 @@ typedef struct {
   int32_t tile_rows;    /* as ipfp_options.tile_rows, for every request     */
   double lane_pairs[3]; /* rising upper bounds of N*M for lanes 0..lanes-2;
                            0 = split log2(N*M) in [20, 36] evenly           */
+  int32_t lane_blocks;  /* reduction workgroups per pass a lane admits up
+                           to; 0 = 2048 (8 per compute unit)                */
+  double aging_ms;      /* waiting time worth a halving of N*M; 0 = 1000    */
 } ipfp_server_options;
 
 enum { IPFP_REQ_QUEUED = 0, IPFP_REQ_RUNNING = 1, IPFP_REQ_FINISHED = 2 };

@@ -384,8 +384,8 @@ class Server:
     them on the device."""
 
     def __init__(self, arena_bytes=1 << 30, max_active=256, lanes=3, chunk=4,
-                 compute="bf16", tile_rows=0, lane_pairs=(0.0, 0.0, 0.0), ctx=None,
-                 device=0):
+                 compute="bf16", tile_rows=0, lane_pairs=(0.0, 0.0, 0.0), lane_blocks=0,
+                 aging_ms=0.0, ctx=None, device=0):
         o = _lib.ServerOptions()
         library().ipfp_default_server_options(ctypes.byref(o))
         o.arena_bytes = int(arena_bytes)
@@ -396,6 +396,8 @@ class Server:
         o.tile_rows = int(tile_rows)
         for k, v in enumerate(lane_pairs):
             o.lane_pairs[k] = float(v)
+        o.lane_blocks = int(lane_blocks)
+        o.aging_ms = float(aging_ms)
         self.compute = compute
         self.ctx = ctx or Context.default(device)
         h = ctypes.c_void_p()

@@ -55,6 +55,7 @@ class ServerOptions(ctypes.Structure):
         ("arena_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
         ("lanes", ctypes.c_int32), ("chunk", ctypes.c_int32), ("compute", ctypes.c_int),
         ("tile_rows", ctypes.c_int32), ("lane_pairs", ctypes.c_double * 3),
+        ("lane_blocks", ctypes.c_int32), ("aging_ms", ctypes.c_double),
     ]
 
 

@@ -1,10 +1,13 @@
 // Serving: continuous batching of many independent markets on one device.
 //
 // A scheduler thread owns every device-side action of the server. Requests
-// wait in a FIFO queue; the head is admitted while its footprint fits the
-// arena (one device slab with a first-fit allocator) and a control-block slot
-// is free. Admission packs the market on the stream ("lane") of its size
-// class. Each lane runs rounds: a round is `chunk` sweeps over all markets
+// wait in a queue and are admitted smallest first (by log2(N M), less their
+// waiting time over an aging constant) while the footprint fits the arena
+// (one device slab with a first-fit allocator), a control-block slot is free
+// and the lane of the request's size class holds fewer reduction workgroups
+// than a fill target: a lane that already fills the chip gains nothing from
+// another market but would share its time with it. Admission packs the market
+// on its lane's stream. Each lane runs rounds: a round is `chunk` sweeps over all markets
 // resident on the lane, each sweep being seven grouped launches (row pass,
 // combine, fixup, convergence check, column pass, combine, fixup) whose grids
 // concatenate the markets' single-market grids, followed by one copy of the
@@ -90,6 +93,8 @@ struct Req {
   ipfp_options opt{};
   ipfp_result* res = nullptr;
   size_t bytes = 0;
+  int64_t blocks = 0;       // workgroups of its row pass
+  int lane_hint = 0;        // lane of its size class
   int state = kQueued;      // guarded by the server mutex
   int code = IPFP_OK;
   int lane = -1;
@@ -137,6 +142,7 @@ struct Lane {
   const int32_t *row_cf = nullptr, *col_cf = nullptr;
   int row_ctot = 0, col_ctot = 0;
   std::vector<PassKey> keys;
+  int64_t blocks = 0;       // row-pass workgroups of active + joining markets
 };
 
 }  // namespace
@@ -437,6 +443,7 @@ void mark_finished(ipfp_server* srv, Req* r, int code) {
 // The market's device loop has stopped (or it was cancelled): enqueue the
 // output copies on its lane and wait for them before releasing its memory.
 void retire(ipfp_server* srv, Lane& L, Req* r) {
+  L.blocks -= r->blocks;
   const Ctl& c = r->last;
   const int code = final_code(r);
   const ipfp_handle* h = r->h;
@@ -489,6 +496,19 @@ void finish_retired(ipfp_server* srv, Req* r, bool copy_failed) {
   mark_finished(srv, r, code);
 }
 
+// A launch or copy on the lane failed: its markets finish with IPFP_EHIP.
+void fail_lane(ipfp_server* srv, Lane& L) {
+  (void)hipStreamSynchronize(L.s);
+  std::vector<Req*> all;
+  all.swap(L.active);
+  for (Req* r : all) {
+    L.blocks -= r->blocks;
+    release_req(srv, r);
+    mark_finished(srv, r, IPFP_EHIP);   // r may be freed by a poller from here on
+  }
+  L.dirty = true;
+}
+
 void after_round(ipfp_server* srv, Lane& L) {
   std::vector<Req*> keep;
   for (Req* r : L.active) {
@@ -528,8 +548,9 @@ bool admit(ipfp_server* srv, Req* r) {
   r->h = h;
   r->off = off;
   r->slot = slot;
-  const int lane = lane_for(srv, h->N, h->M);
+  const int lane = r->lane_hint;
   Lane& L = srv->lanes[lane];
+  L.blocks += r->blocks;
   hipError_t e = hipStreamWaitEvent(L.s, r->ready, 0);
   if (e == hipSuccess) e = handle_setup(h, nullptr, IPFP_F32, 0, L.s);
   {
@@ -546,6 +567,7 @@ bool admit(ipfp_server* srv, Req* r) {
     // nothing of this market is in flight beyond what failed to enqueue:
     // wait for the lane before handing the memory back
     (void)hipStreamSynchronize(L.s);
+    L.blocks -= r->blocks;
     release_req(srv, r);
     mark_finished(srv, r, IPFP_EHIP);
     return true;
@@ -567,13 +589,7 @@ void scheduler(ipfp_server* srv) {
       L.busy = false;
       progress = true;
       if (q != hipSuccess) {
-        (void)hipStreamSynchronize(L.s);
-        for (Req* r : L.active) {
-          release_req(srv, r);
-          mark_finished(srv, r, IPFP_EHIP);
-        }
-        L.active.clear();
-        L.dirty = true;
+        fail_lane(srv, L);
         continue;
       }
       after_round(srv, L);
@@ -591,14 +607,28 @@ void scheduler(ipfp_server* srv) {
       finish_retired(srv, r, q != hipSuccess);
       progress = true;
     }
-    // admission, in submission order
+    // admission: smallest aged size first, among requests whose lane has room
     for (;;) {
       Req* head = nullptr;
       {
         std::lock_guard<std::mutex> g(srv->mu);
-        if (!srv->queue.empty()) {
-          head = srv->queue.front();
-          srv->queue.pop_front();
+        const double now = now_ms();
+        double best = INFINITY;
+        size_t at = 0;
+        for (size_t q = 0; q < srv->queue.size(); ++q) {
+          Req* r = srv->queue[q];
+          const Lane& L = srv->lanes[r->lane_hint];
+          if (L.blocks > 0 && L.blocks + r->blocks > srv->opt.lane_blocks) continue;
+          const double key = log2((double)r->mk.N * (double)r->mk.M) -
+                             (now - r->t_submit) / srv->opt.aging_ms;
+          if (key < best) {
+            best = key;
+            head = r;
+            at = q;
+          }
+        }
+        if (head) {
+          srv->queue.erase(srv->queue.begin() + at);
           head->state = kAdmitting;
           srv->stats.queued -= 1;
         }
@@ -617,9 +647,9 @@ void scheduler(ipfp_server* srv) {
         srv->done_cv.notify_all();
         continue;
       }
-      head->state = kQueued;
+      head->state = kQueued;      // waits for memory or a slot
       srv->stats.queued += 1;
-      srv->queue.push_front(head);
+      srv->queue.push_back(head);
       break;
     }
     // new rounds on idle lanes
@@ -629,15 +659,7 @@ void scheduler(ipfp_server* srv) {
       if (!L.busy && (!L.active.empty() || !L.joining.empty())) {
         const hipError_t e = start_round(srv, L);
         progress = true;
-        if (e != hipSuccess) {
-          (void)hipStreamSynchronize(L.s);
-          for (Req* r : L.active) {
-            release_req(srv, r);
-            mark_finished(srv, r, IPFP_EHIP);
-          }
-          L.active.clear();
-          L.dirty = true;
-        }
+        if (e != hipSuccess) fail_lane(srv, L);
       }
       any_work = any_work || L.busy || !L.active.empty() || !L.joining.empty();
     }
@@ -710,6 +732,8 @@ void ipfp_default_server_options(ipfp_server_options* opt) {
   opt->chunk = 4;
   opt->compute = IPFP_BF16;
   opt->tile_rows = 0;
+  opt->lane_blocks = 2048;
+  opt->aging_ms = 1000.0;
 }
 
 int ipfp_server_create(ipfp_ctx* ctx, const ipfp_server_options* opt, ipfp_server** out) {
@@ -725,11 +749,14 @@ int ipfp_server_create(ipfp_ctx* ctx, const ipfp_server_options* opt, ipfp_serve
     o.compute = opt->compute;
     o.tile_rows = opt->tile_rows;
     for (int k = 0; k < 3; ++k) o.lane_pairs[k] = opt->lane_pairs[k];
+    if (opt->lane_blocks) o.lane_blocks = opt->lane_blocks;
+    if (opt->aging_ms != 0.0) o.aging_ms = opt->aging_ms;
   }
   if (o.max_active < 1 || o.max_active > 1024 || o.lanes < 1 || o.lanes > kMaxLanes ||
       o.chunk < 1 || o.chunk > 64)
     return IPFP_EINVAL;
   if (o.compute != IPFP_BF16 && o.compute != IPFP_FP8E4M3) return IPFP_EINVAL;
+  if (o.lane_blocks < 1 || !(o.aging_ms > 0.0)) return IPFP_EINVAL;
   if (o.tile_rows != 0 && o.tile_rows != 128 && o.tile_rows != 256 && o.tile_rows != 512)
     return IPFP_EINVAL;
   ipfp_server* srv = new ipfp_server;
@@ -805,6 +832,9 @@ int ipfp_submit(ipfp_server* srv, const ipfp_market* mk, const ipfp_options* opt
   rc = ipfp_footprint(mk, &o, &bytes);
   if (rc != IPFP_OK) return rc;
   if (bytes > srv->arena.cap()) return IPFP_EBUDGET;
+  const int64_t kpad = fused_kpad(mk->d, o.compute);
+  const int rx = fused_rows_per_wg(kpad, o.compute, o.tile_rows > 0 ? o.tile_rows : 512);
+  const int sx = o.splits > 0 ? o.splits : fused_auto_splits(mk->N, mk->M, rx);
   if (hipSetDevice(srv->ctx->device) != hipSuccess) return IPFP_EHIP;
   hipEvent_t ready = nullptr;
   if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return IPFP_EHIP;
@@ -818,6 +848,8 @@ int ipfp_submit(ipfp_server* srv, const ipfp_market* mk, const ipfp_options* opt
   r->opt = o;
   r->res = res;
   r->bytes = bytes;
+  r->blocks = (mk->N + rx - 1) / rx * sx;
+  r->lane_hint = lane_for(srv, mk->N, mk->M);
   r->t_submit = now_ms();
   {
     std::lock_guard<std::mutex> g(srv->mu);

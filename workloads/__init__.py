@@ -185,3 +185,19 @@ def serving_requests(count: int = 512, rate_hz: float = 200.0,
 def request_market(r: Request) -> Market:
     return factor_market(r.N, r.M, r.d, 1.0 / r.d, r.sigma, "unit", r.seed,
                          name=f"req{r.index}")
+
+
+def device_request_factors(torch, r: Request, device="cuda"):
+    """(U, Q, V, P, n, m) of a serving request drawn directly on the device:
+    the distribution of ``request_market`` (i.i.d. N(0, 1/d) float32 factors,
+    unit margins) from torch's device generator seeded with the request's
+    seed, so a large request mix never passes through host memory. The
+    numbers differ from ``request_market``'s (another generator)."""
+    g = torch.Generator(device=device)
+    g.manual_seed(r.seed)
+    sd = math.sqrt(1.0 / r.d)
+    U, Q = (torch.randn(r.N, r.d, generator=g, device=device) * sd for _ in range(2))
+    V, P = (torch.randn(r.M, r.d, generator=g, device=device) * sd for _ in range(2))
+    n = torch.ones(r.N, dtype=torch.float64, device=device)
+    m = torch.ones(r.M, dtype=torch.float64, device=device)
+    return U, Q, V, P, n, m
