@@ -37,9 +37,9 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, verbose: bool, build_dir: str, defines=()) -> str:
+def _compile(src: str, verbose: bool, build_dir: str, defines=(), flags=()) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *HIPCC_FLAGS, *(f"-D{d}" for d in defines), "-c",
+    cmd = [hipcc(), *HIPCC_FLAGS, *flags, *(f"-D{d}" for d in defines), "-c",
            os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -53,12 +53,14 @@ def _compile(src: str, verbose: bool, build_dir: str, defines=()) -> str:
     return obj
 
 
-def build(verbose: bool = False, out: str = LIB, defines=(), build_dir: str = BUILD_DIR) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=(), build_dir: str = BUILD_DIR,
+          flags=()) -> str:
     """Compile every source and link libipfp.so (or `out`); returns its path.
-    `defines` are NAME=VALUE tuning macros (e.g. IPFP_TY=128)."""
+    `defines` are NAME=VALUE tuning macros (e.g. IPFP_TY=128), `flags` extra
+    hipcc options."""
     os.makedirs(build_dir, exist_ok=True)
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose, build_dir, defines), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, build_dir, defines, flags), SOURCES))
     tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -168,6 +168,7 @@ struct Op<true> {  // FP8 e4m3, v_mfma_scale_f32_32x32x64_f8f6f4
 #ifndef IPFP_TY
 #define IPFP_TY 128
 #endif
+
 constexpr int ty_for(int row_bytes) { return row_bytes <= 256 ? IPFP_TY : IPFP_TY / 2; }
 
 // Binary exponent e with w = m 2^e, m in [0.5, 1) (INT_MIN for w = 0).
@@ -321,17 +322,17 @@ __device__ __forceinline__ void fused_pass_body(
   intx4 pre[CPT];
   float pw = 0.f;
   int psc = 127;
+  // Row arithmetic is 32-bit (L < 2^31): one 32x32->64 multiply-add per load.
   auto gload = [&](int tile) {
-    const int64_t y0 = (int64_t)tile * kTY;
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int chunk = min(tid + q * NT, CH - 1);
       const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
-      const int64_t y = min(y0 + r, (int64_t)L - 1);
-      pre[q] = *reinterpret_cast<const intx4*>(Yr + y * RB + cb * 16);
+      const uint32_t y = (uint32_t)min(tile * kTY + r, L - 1);
+      pre[q] = *reinterpret_cast<const intx4*>(Yr + cb * 16 + (uint64_t)y * RB);
     }
-    const int64_t y = y0 + (tid % kTY);
-    const int64_t yc = min(y, (int64_t)L - 1);
+    const int y = tile * kTY + (tid % kTY);
+    const int yc = min(y, L - 1);
     if (!MAXMODE) {
       const float wv = (float)ldexp(wred[yc], -E);
       pw = y < L ? wv : 0.f;
@@ -404,17 +405,24 @@ __device__ __forceinline__ void fused_pass_body(
       for (int sub = 0; sub < SUB; ++sub) {
         const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
         const int asc = FP8 ? ysc[buf][sub * 32 + l32] : 127;
+        // the XT accumulators advance together: independent MFMA chains
+        floatx16 acc[XT];
+#pragma unroll
+        for (int t = 0; t < XT; ++t) acc[t] = shv[t];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const Frag f = lds_frag<FP8, Frag>(arow, s);
+#pragma unroll
+          for (int t = 0; t < XT; ++t)
+            acc[t] = mfma_step<FP8>(f, bfrag[t][s], acc[t], asc, xsc[t]);
+        }
 #pragma unroll
         for (int t = 0; t < XT; ++t) {
-          floatx16 acc = shv[t];
-#pragma unroll
-          for (int s = 0; s < NS; ++s)
-            acc = mfma_step<FP8>(lds_frag<FP8, Frag>(arow, s), bfrag[t][s], acc, asc, xsc[t]);
-          float m0 = fmaxf(acc[0], acc[1]), m1 = fmaxf(acc[2], acc[3]);
+          float m0 = fmaxf(acc[t][0], acc[t][1]), m1 = fmaxf(acc[t][2], acc[t][3]);
 #pragma unroll
           for (int r = 4; r < 16; r += 2) {
-            m0 = fmaxf(m0, acc[r]);
-            m1 = fmaxf(m1, acc[r + 1]);
+            m0 = fmaxf(m0, acc[t][r]);
+            m1 = fmaxf(m1, acc[t][r + 1]);
           }
           mx[t] = fmaxf(mx[t], fmaxf(m0, m1));
         }
