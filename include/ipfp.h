@@ -199,7 +199,34 @@ int ipfp_mu_pairs(ipfp_ctx *ctx, const ipfp_market *mk, const double *a,
                   const double *b, const int64_t *xs, const int64_t *ys,
                   int64_t count, double *mu_out, void *stream);
 
-/* The fused path's packed operand of one side (Sec. 3.3's factor matrices as
+/* Stable factors of eq. 11 (Alg. 2's outputs), with which the matching of
+ * eq. 4 factorises as log mu_xy = <psi_x, xi_y> / (2 sigma):
+ *   psi_x = [U_x, Q_x, 2 sigma log a_x, 1],  xi_y = [V_y, P_y, 1, 2 sigma log b_y].
+ * The paper prints sigma log u in place of 2 sigma log u; with u = sqrt(mu_x0)
+ * only the factor 2 reproduces eq. 4, so that is what is written.
+ * psi: N x (2d + 2) FP64 device matrix with row stride ld_psi; xi: M x (2d + 2)
+ * with ld_xi (both caller-owned). Factors are read as given (mk->in_dtype);
+ * the margins are not read. */
+int ipfp_stable_factors(ipfp_ctx *ctx, const ipfp_market *mk, const double *a,
+                        const double *b, double *psi, int64_t ld_psi, double *xi,
+                        int64_t ld_xi, void *stream);
+
+/* Recommendation lists of a resident fused market at its current state: for
+ * side 0 every candidate x gets the k employers y with the largest mu_xy, for
+ * side 1 every employer y the k candidates x with the largest mu_xy (the
+ * reciprocal recommendation of Sec. 4.1, ranked by the stable matching).
+ * Scores are formed from the packed operands the solve uses: log mu_xy =
+ * ln 2 (T_xy + log2 a_x + log2 b_y), T from the matrix cores in FP32. idx_out
+ * (rows x k int32, device) lists indices best first, score_out (rows x k
+ * float, device) the matching log mu; entries beyond the other side's size
+ * are -1 / -inf. Equal scores keep the lower index of a lane's stream, so the
+ * order among exact ties is implementation-defined. 1 <= k <= 32. Scratch of
+ * splits x rows x (4 + 4) x k' bytes (k' = 8, 16 or 32) is allocated for the
+ * call and charged to the context budget. */
+int ipfp_market_topk(ipfp_handle *h, int side, int32_t k, int32_t *idx_out,
+                     float *score_out, void *stream);
+
+/* The fused path's packed operand of one side/* The fused path's packed operand of one side (Sec. 3.3's factor matrices as
  * the matrix cores read them): rows p [A|B] concatenated, zero-padded to
  * `kpad` columns and rounded to `compute`, where p = sqrt(log2(e)/(2 sigma))
  * rounded to FP32 (p = 1 when sigma = 0), applied in FP32 after rounding the

@@ -28,6 +28,8 @@ closed forms in ``oracle.closed`` and the invariants checked in the test
 suite. ``ipfp_minibatch`` and ``half_step_rows`` are pinned against
 ``ipfp_batch`` (the paper states the mini-batch form is exact) and against the
 closed forms. ``stable_factors`` is pinned against log(mu) of ``matching``.
+``topk_matches`` is pinned against a selection loop that repeatedly takes the
+largest remaining entry.
 """
 from __future__ import annotations
 
@@ -234,6 +236,22 @@ def stable_factors(U, Q, V, P, a, b, sigma: float):
     xi = np.concatenate([np.asarray(V, np.float64), np.asarray(P, np.float64),
                          np.ones((M, 1)), (2.0 * sigma * np.log(b))[:, None]], 1)
     return psi, xi
+
+
+def topk_matches(logmu, k: int):
+    """Recommendation lists from a matching (Sec. 4.1 ranks partners by the
+    stable matching mu): for every row, the columns of the k largest log mu,
+    best first, ties to the lower column; rows shorter than k are padded with
+    index -1 and -inf. Returns (idx int64 rows x k, values rows x k)."""
+    logmu = np.asarray(logmu, dtype=np.float64)
+    R, C = logmu.shape
+    order = np.argsort(-logmu, axis=1, kind="stable")[:, :k]
+    vals = np.take_along_axis(logmu, order, axis=1)
+    idx = np.full((R, k), -1, dtype=np.int64)
+    out = np.full((R, k), -np.inf)
+    idx[:, :order.shape[1]] = order
+    out[:, :order.shape[1]] = vals
+    return idx, out
 
 
 def pair_evals(N: int, M: int, sweeps: int) -> int:

@@ -22,7 +22,7 @@ from . import _lib
 
 __all__ = ["IPFPError", "Context", "SolveInfo", "solve_market", "solve_market_phi",
            "Market", "mu_pairs", "pack_side", "footprint", "library", "Server", "Request",
-           "clock_ms"]
+           "clock_ms", "stable_factors"]
 
 _DT = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "fp8": _lib.FP8E4M3,
        "fp8e4m3": _lib.FP8E4M3}
@@ -273,6 +273,20 @@ class Market:
                       "ipfp_market_read")
         return a, b, _info(code, r, hist)
 
+    def topk(self, k: int, side: int = 0):
+        """Recommendation lists at the current state (``ipfp_market_topk``):
+        (indices int32 rows x k, log mu float32 rows x k), best first; side 0
+        ranks employers for every candidate, side 1 candidates for every
+        employer."""
+        torch = _torch()
+        rows = self._mk.N if side == 0 else self._mk.M
+        idx = torch.empty((rows, k), dtype=torch.int32, device=self.device)
+        score = torch.empty((rows, k), dtype=torch.float32, device=self.device)
+        _check(library().ipfp_market_topk(self.handle, int(side), int(k), idx.data_ptr(),
+                                          score.data_ptr(), _stream_ptr(self.stream)),
+               "ipfp_market_topk")
+        return idx, score
+
     def close(self):
         if getattr(self, "handle", None):
             library().ipfp_market_close(self.handle)
@@ -305,6 +319,22 @@ def mu_pairs(U, Q, V, P, sigma, a, b, xs, ys, stream=None, ctx=None):
                                    b.data_ptr(), xs.data_ptr(), ys.data_ptr(), xs.numel(),
                                    out.data_ptr(), _stream_ptr(stream)), "ipfp_mu_pairs")
     return out
+
+
+def stable_factors(U, Q, V, P, sigma, a, b, stream=None, ctx=None):
+    """(psi, xi) of eq. 11: log mu_xy = <psi_x, xi_y> / (2 sigma), FP64."""
+    torch = _torch()
+    n_dummy = torch.ones(U.shape[0], dtype=torch.float64, device=U.device)
+    m_dummy = torch.ones(V.shape[0], dtype=torch.float64, device=U.device)
+    mk = _market_struct(U, Q, V, P, n_dummy, m_dummy, sigma)
+    w = 2 * mk.d + 2
+    psi = torch.empty((mk.N, w), dtype=torch.float64, device=U.device)
+    xi = torch.empty((mk.M, w), dtype=torch.float64, device=U.device)
+    ctx = ctx or Context.default(U.device.index or 0)
+    _check(library().ipfp_stable_factors(ctx.handle, ctypes.byref(mk), a.data_ptr(),
+                                         b.data_ptr(), psi.data_ptr(), w, xi.data_ptr(), w,
+                                         _stream_ptr(stream)), "ipfp_stable_factors")
+    return psi, xi
 
 
 def pack_side(A, B, compute="bf16", sigma=0.0, stream=None, ctx=None):

@@ -113,6 +113,11 @@ SIGNATURES = {
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "ipfp_stable_factors": (ctypes.c_int, [
+        ctypes.c_void_p, ctypes.POINTER(Market), ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "ipfp_market_topk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ipfp_default_server_options": (None, [ctypes.POINTER(ServerOptions)]),
     "ipfp_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerOptions),
                                           ctypes.POINTER(ctypes.c_void_p)]),

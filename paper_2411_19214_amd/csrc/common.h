@@ -141,6 +141,18 @@ hipError_t launch_fused_fixup(const FusedPass& fp, double* w2, int dbuf,
 hipError_t launch_init_exp(const double* w, int64_t len, Ctl* ctl, int idx,
                            hipStream_t s);
 
+// Recommendation lists (top-k per output row of a pass's output side): the
+// k reduced rows with the largest mu, as (index, log mu). Scratch: splits x
+// rows x topk_width(k) floats (pscore) and int32 (pidx).
+int topk_width(int k);
+int topk_splits(int64_t R, int64_t L);
+hipError_t launch_topk(const FusedPass& fp, const double* a_out, int k, int splits,
+                       float* pscore, int32_t* pidx, int32_t* idx_out, float* score_out,
+                       hipStream_t s);
+hipError_t launch_stable_factors(const void* A, const void* B, ipfp_dtype dt, int64_t ld,
+                                 int64_t rows, int64_t d, double sigma, const double* w,
+                                 int log_col, double* out, int64_t ld_out, hipStream_t s);
+
 // ---- grouped launches (many resident markets per kernel launch) -------------
 
 // One market's half-sweep as the grouped pass, combine and fixup kernels read

@@ -131,6 +131,40 @@ __device__ __forceinline__ double ld_elem(const void* p, int64_t i,
 
 // mu_xy = exp(Phi_xy / 2 sigma) a_x b_y at requested pairs (eq. 4), with the
 // surplus formed in FP64 from the factors as given.
+// Stable factors (eq. 11): one output row [A_x, B_x, c0, c1] of 2d + 2 FP64
+// values, with the log entry 2 sigma log w_x in column 2d + log_col and 1 in
+// the other (2 sigma, not the printed sigma: with w = sqrt of the unmatched
+// mass this is sigma log mu_x0, which makes the inner product reproduce
+// eq. 4).
+__global__ void k_stable_factors(const void* A, const void* B, ipfp_dtype dt, int64_t ld,
+                                 int64_t rows, int64_t d, double sigma, const double* w,
+                                 int log_col, double* out, int64_t ld_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t width = 2 * d + 2;
+  if (i >= rows * width) return;
+  const int64_t r = i / width, c = i % width;
+  double v;
+  if (c < d) {
+    v = ld_elem(A, r * ld + c, dt);
+  } else if (c < 2 * d) {
+    v = ld_elem(B, r * ld + (c - d), dt);
+  } else if (c - 2 * d == log_col) {
+    v = 2.0 * sigma * log(w[r]);
+  } else {
+    v = 1.0;
+  }
+  out[r * ld_out + c] = v;
+}
+
+hipError_t launch_stable_factors(const void* A, const void* B, ipfp_dtype dt, int64_t ld,
+                                 int64_t rows, int64_t d, double sigma, const double* w,
+                                 int log_col, double* out, int64_t ld_out, hipStream_t s) {
+  const int64_t n = rows * (2 * d + 2);
+  hipLaunchKernelGGL(k_stable_factors, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     A, B, dt, ld, rows, d, sigma, w, log_col, out, ld_out);
+  return hipGetLastError();
+}
+
 __global__ void k_mu_pairs(const void* U, const void* Q, const void* V,
                            const void* P, ipfp_dtype dt, int64_t ld_x,
                            int64_t ld_y, int64_t N, int64_t M, int64_t d,

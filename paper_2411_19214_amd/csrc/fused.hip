@@ -554,6 +554,254 @@ __global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu
       (int)blockIdx.x - __builtin_amdgcn_readfirstlane(first[j]));
 }
 
+// ---- recommendation lists: top-k per output row -------------------------------
+//
+// After the solve, mu_or = 2^(T_or) a_o w_r (eq. 4 with K in log2 units), so
+// for a fixed output row o the reduced rows ranked by mu are ranked by the
+// score T_or + log2 w_r. This pass forms T on the matrix cores exactly as the
+// reduction pass does and keeps, per lane, the KT best (score, row) pairs in
+// registers, sorted descending (ties keep the earlier row of the lane's
+// stream). The two lanes that share an output row merge at the end; one
+// partial list per (split, row) goes to memory and k_topk_merge combines the
+// splits in fixed order.
+
+// Inserts (s, i) into the descending list (ts, ti), dropping its last entry.
+template <int KT>
+__device__ __forceinline__ void topk_insert(float (&ts)[KT], int (&ti)[KT], float s, int i) {
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    const bool sw = s > ts[j];
+    const float t = ts[j];
+    const int u = ti[j];
+    ts[j] = sw ? s : t;
+    ti[j] = sw ? i : u;
+    s = sw ? t : s;
+    i = sw ? u : i;
+  }
+}
+
+template <int KP, bool FP8, int KT>
+__global__ void __launch_bounds__(256)
+    k_topk_pass(const uint8_t* __restrict__ Xo, const float* __restrict__ xscale,
+                const uint8_t* __restrict__ Yr, const float* __restrict__ yscale,
+                const double* __restrict__ wred, int R, int L, int tiles_per_split,
+                int nsplit, float* __restrict__ pscore, int32_t* __restrict__ pidx) {
+  constexpr int WAVES = 4;
+  typedef PassCore<KP, 1, WAVES, FP8> C;
+  typedef typename C::Frag Frag;
+  typedef Op<FP8> O;
+  constexpr int RB = C::RB, kTY = C::kTY, NS = C::NS, LS = C::LS, NT = C::NT;
+  constexpr int CH = C::CH, CPT = C::CPT, SUB = C::SUB;
+  __shared__ __attribute__((aligned(16))) uint8_t ys[2][kTY * LS];
+  __shared__ __attribute__((aligned(16))) float lws[2][kTY];
+  __shared__ int32_t ysc[2][kTY];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int split = blockIdx.x % nsplit, rb = blockIdx.x / nsplit;
+  const int T = (L + kTY - 1) / kTY;
+  const int t0 = split * tiles_per_split, t1 = min(T, t0 + tiles_per_split);
+  const int x = (rb * WAVES + wave) * 32 + l32;
+  const bool ok = x < R;
+
+  Frag bfrag[NS];
+  {
+    const uint8_t* src = Xo + (int64_t)(ok ? x : 0) * RB + h * O::SB;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      Frag f = lds_frag<FP8, Frag>(src, s);
+      if (!ok) *reinterpret_cast<intx4*>(&f) = intx4{0, 0, 0, 0};
+      if constexpr (FP8) {
+        if (!ok) reinterpret_cast<intx4*>(&f)[1] = intx4{0, 0, 0, 0};
+      }
+      bfrag[s] = f;
+    }
+  }
+  const int xsc = FP8 && ok ? (int)((__float_as_uint(xscale[x]) >> 23) & 0xFF) : 127;
+
+  float ts[KT];
+  int ti[KT];
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    ts[j] = -INFINITY;
+    ti[j] = -1;
+  }
+
+  // stage loader (as in the reduction pass): rows past the end are clamped and
+  // get score -inf through lw
+  intx4 pre[CPT];
+  float plw = -INFINITY;
+  int psc = 127;
+  auto gload = [&](int tile) {
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int chunk = min(tid + q * NT, CH - 1);
+      const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
+      const uint32_t y = (uint32_t)min(tile * kTY + r, L - 1);
+      pre[q] = *reinterpret_cast<const intx4*>(Yr + cb * 16 + (uint64_t)y * RB);
+    }
+    const int y = tile * kTY + (tid % kTY);
+    const int yc = min(y, L - 1);
+    plw = y < L ? (float)log2(wred[yc]) : -INFINITY;
+    if (FP8) psc = (int)((__float_as_uint(yscale[yc]) >> 23) & 0xFF);
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int chunk = min(tid + q * NT, CH - 1);
+      const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
+      *reinterpret_cast<intx4*>(&ys[buf][r * LS + cb * 16]) = pre[q];
+    }
+    lws[buf][tid % kTY] = plw;
+    if (FP8) ysc[buf][tid % kTY] = psc;
+  };
+
+  if (t0 < t1) {
+    gload(t0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int tile = t0; tile < t1; ++tile) {
+    const int buf = (tile - t0) & 1;
+    gload(min(tile + 1, t1 - 1));
+#pragma unroll
+    for (int sub = 0; sub < SUB; ++sub) {
+      const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
+      const int asc = FP8 ? ysc[buf][sub * 32 + l32] : 127;
+      floatx16 acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        acc = mfma_step<FP8>(lds_frag<FP8, Frag>(arow, s), bfrag[s], acc, asc, xsc);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int yr = sub * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const float sc = acc[r] + lws[buf][yr];
+        if (sc > ts[KT - 1]) topk_insert<KT>(ts, ti, sc, tile * kTY + yr);
+      }
+    }
+    lstore(buf ^ 1);
+    __syncthreads();
+  }
+  // lanes l and l + 32 hold the same output row: merge into the lower one
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    const float s = __shfl_xor(ts[j], 32, 64);
+    const int i = __shfl_xor(ti[j], 32, 64);
+    if (h == 0 && s > ts[KT - 1]) topk_insert<KT>(ts, ti, s, i);
+  }
+  if (h == 0 && ok) {
+    const int64_t base = ((int64_t)split * R + x) * KT;
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+      pscore[base + j] = ts[j];
+      pidx[base + j] = ti[j];
+    }
+  }
+}
+
+// Merges the split lists of every row (fixed split order) and writes the k
+// best as (row index, log mu): log mu_or = ln 2 (score + log2 a_o).
+template <int KT>
+__global__ void __launch_bounds__(256)
+    k_topk_merge(const float* __restrict__ pscore, const int32_t* __restrict__ pidx,
+                 int nsplit, int R, const double* __restrict__ a_out, int k,
+                 int32_t* __restrict__ idx_out, float* __restrict__ score_out) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= R) return;
+  float ts[KT];
+  int ti[KT];
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    ts[j] = -INFINITY;
+    ti[j] = -1;
+  }
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const int64_t base = ((int64_t)sp * R + o) * KT;
+    for (int j = 0; j < KT; ++j) {
+      const float s = pscore[base + j];
+      if (!(s > ts[KT - 1])) break;   // lists are sorted: the rest is smaller
+      topk_insert<KT>(ts, ti, s, pidx[base + j]);
+    }
+  }
+  const double la = log2(a_out[o]);
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    if (j < k) {
+      idx_out[(int64_t)o * k + j] = ti[j];
+      score_out[(int64_t)o * k + j] =
+          ti[j] >= 0 ? (float)(((double)ts[j] + la) * 0.6931471805599453) : -INFINITY;
+    }
+  }
+}
+
+template <int KP, bool FP8, int KT>
+static hipError_t topk_t(const FusedPass& fp, const double* a_out, int k, int splits,
+                         float* pscore, int32_t* pidx, int32_t* idx_out, float* score_out,
+                         hipStream_t s) {
+  constexpr int kTY = ty_for(KP * Op<FP8>::ES);
+  const int64_t rblocks = (fp.out.rows + 127) / 128;
+  const int T = (int)((fp.red.rows + kTY - 1) / kTY);
+  const int tps = (T + splits - 1) / splits;
+  hipLaunchKernelGGL((k_topk_pass<KP, FP8, KT>), dim3((unsigned)(rblocks * splits)),
+                     dim3(256), 0, s, (const uint8_t*)fp.out.ops, fp.out.scale,
+                     (const uint8_t*)fp.red.ops, fp.red.scale, fp.w_red, (int)fp.out.rows,
+                     (int)fp.red.rows, tps, splits, pscore, pidx);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_topk_merge<KT>), dim3((unsigned)((fp.out.rows + 255) / 256)),
+                     dim3(256), 0, s, pscore, pidx, splits, (int)fp.out.rows, a_out, k,
+                     idx_out, score_out);
+  return hipGetLastError();
+}
+
+template <int KP, bool FP8>
+static hipError_t topk_kp(const FusedPass& fp, const double* a_out, int k, int splits,
+                          float* pscore, int32_t* pidx, int32_t* idx_out, float* score_out,
+                          hipStream_t s) {
+  const int kt = topk_width(k);
+  if (kt == 8)
+    return topk_t<KP, FP8, 8>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
+  if (kt == 16)
+    return topk_t<KP, FP8, 16>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
+  return topk_t<KP, FP8, 32>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
+}
+
+int topk_width(int k) { return k <= 8 ? 8 : (k <= 16 ? 16 : 32); }
+
+int topk_splits(int64_t R, int64_t L) { return fused_auto_splits(R, L, 128); }
+
+hipError_t launch_topk(const FusedPass& fp, const double* a_out, int k, int splits,
+                       float* pscore, int32_t* pidx, int32_t* idx_out, float* score_out,
+                       hipStream_t s) {
+  if (k < 1 || k > 32) return hipErrorInvalidValue;
+#define IPFP_TOPK_CASE(KPV, F8)                                                       \
+  case KPV:                                                                           \
+    return topk_kp<KPV, F8>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
+  if (fp.compute == IPFP_FP8E4M3) {
+    switch (fp.kpad) {
+      IPFP_TOPK_CASE(64, true)
+      IPFP_TOPK_CASE(128, true)
+      IPFP_TOPK_CASE(192, true)
+      IPFP_TOPK_CASE(256, true)
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (fp.kpad) {
+    IPFP_TOPK_CASE(32, false)
+    IPFP_TOPK_CASE(64, false)
+    IPFP_TOPK_CASE(96, false)
+    IPFP_TOPK_CASE(128, false)
+    IPFP_TOPK_CASE(160, false)
+    IPFP_TOPK_CASE(192, false)
+    IPFP_TOPK_CASE(224, false)
+    IPFP_TOPK_CASE(256, false)
+    default: return hipErrorInvalidValue;
+  }
+#undef IPFP_TOPK_CASE
+}
+
 // ---- combine partial sums, update scalings -----------------------------------
 
 // Finishes output row o given lS = log2((K w)_o): the residual of the current

@@ -551,6 +551,63 @@ int ipfp_mu_pairs(ipfp_ctx* ctx, const ipfp_market* mk, const double* a,
   return rc;
 }
 
+int ipfp_stable_factors(ipfp_ctx* ctx, const ipfp_market* mk, const double* a,
+                        const double* b, double* psi, int64_t ld_psi, double* xi,
+                        int64_t ld_xi, void* stream) {
+  if (!ctx || !mk || !a || !b || !psi || !xi) return IPFP_EINVAL;
+  if (mk->N < 1 || mk->M < 1 || mk->d < 1 || mk->d > 256 || !(mk->sigma > 0.0)) return IPFP_EINVAL;
+  if (!mk->U || !mk->Q || !mk->V || !mk->P || mk->ld_x < mk->d || mk->ld_y < mk->d)
+    return IPFP_EINVAL;
+  if (mk->in_dtype != IPFP_F64 && mk->in_dtype != IPFP_F32 && mk->in_dtype != IPFP_BF16)
+    return IPFP_EINVAL;
+  const int64_t width = 2 * mk->d + 2;
+  if (ld_psi < width || ld_xi < width) return IPFP_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IPFP_EHIP;
+  HIPCHK(launch_stable_factors(mk->U, mk->Q, mk->in_dtype, mk->ld_x, mk->N, mk->d, mk->sigma,
+                               a, 0, psi, ld_psi, s));
+  HIPCHK(launch_stable_factors(mk->V, mk->P, mk->in_dtype, mk->ld_y, mk->M, mk->d, mk->sigma,
+                               b, 1, xi, ld_xi, s));
+  return IPFP_OK;
+}
+
+int ipfp_market_topk(ipfp_handle* h, int side, int32_t k, int32_t* idx_out, float* score_out,
+                     void* stream) {
+  if (!h || h->plain || (side != 0 && side != 1) || k < 1 || k > 32 || !idx_out || !score_out)
+    return IPFP_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return IPFP_EHIP;
+  int rc = read_ctl(h, s);
+  if (rc != IPFP_OK) return rc;
+  const Ctl c = *h->host_ctl;
+  const int state = c.done ? c.stop_sweep : c.sweep;
+  const double* u = h->u2 + (int64_t)(state & 1) * h->N;
+  FusedPass fp = side == 0 ? h->rowp : h->colp;
+  fp.w_red = side == 0 ? h->v : u;
+  fp.red_dbuf = 0;
+  const double* a_out = side == 0 ? u : h->v;
+  const int64_t R = fp.out.rows, L = fp.red.rows;
+  const int splits = topk_splits(R, L);
+  const size_t entries = (size_t)splits * R * topk_width(k);
+  const size_t bytes = align_up(entries * sizeof(float), 256) + entries * sizeof(int32_t);
+  rc = ctx_reserve(h->ctx, bytes);
+  if (rc != IPFP_OK) return rc;
+  char* mem = nullptr;
+  if (hipMalloc((void**)&mem, bytes) != hipSuccess) {
+    ctx_release(h->ctx, bytes);
+    return IPFP_EBUDGET;
+  }
+  float* pscore = (float*)mem;
+  int32_t* pidx = (int32_t*)(mem + align_up(entries * sizeof(float), 256));
+  rc = IPFP_OK;
+  if (launch_topk(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = IPFP_EHIP;
+  (void)hipFree(mem);
+  ctx_release(h->ctx, bytes);
+  return rc;
+}
+
 int ipfp_pack_side(ipfp_ctx* ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
                    const void* A, const void* B, int64_t ld, ipfp_dtype compute,
                    double sigma, void* out, float* scale_out, int64_t* kpad_out,

@@ -1,0 +1,109 @@
+"""GPU tests of the solve's outputs beyond (a, b): the stable factors of
+eq. 11 and the top-k recommendation lists ranked by the stable matching.
+
+Top-k is an integer decision taken from floating-point scores, and near-ties
+may order differently in the kernel's FP32 and the oracle's FP64. The oracle
+scores the same quantised operands, and the test checks what is unique: every
+returned index is valid and distinct, its score matches the oracle's log mu
+there, the list is sorted, and it holds every entry that beats the k-th best by
+more than the score tolerance, and nothing below it by more than that."""
+import numpy as np
+import pytest
+
+import workloads
+from helpers import banner, market_tensors, require_gpu
+from oracle import ipfp as O, quant
+
+pytestmark = pytest.mark.gpu
+
+# |T| stays below ~30 here; FP32 accumulation of a 128-term product and the
+# FP32 sum with log2 b are good to ~1e-5 in log2 units
+SCORE_TOL = 2e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2411_19214_amd as L
+    return L
+
+
+def test_stable_factors_reproduce_matching(torch, lib):
+    banner("stable factors")
+    mk = workloads.config_market(1)
+    t = market_tensors(torch, mk, torch.float64)
+    a, b, _ = lib.solve_market(*t, mk.sigma, tol=1e-12, max_sweeps=500, path="plain",
+                               compute="f64")
+    psi, xi = lib.stable_factors(t[0], t[1], t[2], t[3], mk.sigma, a, b)
+    psi_r, xi_r = O.stable_factors(mk.U, mk.Q, mk.V, mk.P, a.cpu().numpy(), b.cpu().numpy(),
+                                   mk.sigma)
+    np.testing.assert_allclose(psi.cpu().numpy(), psi_r, rtol=1e-15, atol=1e-15)
+    np.testing.assert_allclose(xi.cpu().numpy(), xi_r, rtol=1e-15, atol=1e-15)
+    # log mu_xy = <psi_x, xi_y> / 2 sigma against the library's own mu output
+    xs = torch.arange(0, mk.N, 7, device="cuda")
+    ys = torch.arange(0, mk.N, 7, device="cuda") % mk.M
+    mu = lib.mu_pairs(*t[:4], mk.sigma, a, b, xs, ys).cpu().numpy()
+    lm = (psi[xs] * xi[ys]).sum(1).cpu().numpy() / (2 * mk.sigma)
+    np.testing.assert_allclose(lm, np.log(mu), rtol=0, atol=1e-12)
+
+
+def check_lists(idx, score, ref_logmu, k):
+    R, C = ref_logmu.shape
+    ref_idx, ref_val = O.topk_matches(ref_logmu, k)
+    for r in range(R):
+        got = idx[r]
+        valid = got[got >= 0]
+        assert len(valid) == min(k, C), (r, got)
+        assert len(set(valid.tolist())) == len(valid)
+        assert np.all(got[len(valid):] == -1) and np.all(np.isneginf(score[r, len(valid):]))
+        s = score[r, :len(valid)].astype(np.float64)
+        assert np.all(np.diff(s) <= 1e-6), (r, s)
+        np.testing.assert_allclose(s, ref_logmu[r, valid], rtol=0, atol=SCORE_TOL)
+        kth = ref_val[r, len(valid) - 1]
+        must = np.nonzero(ref_logmu[r] > kth + SCORE_TOL)[0]
+        assert set(must.tolist()) <= set(valid.tolist()), (r, must, valid)
+        assert np.all(ref_logmu[r, valid] >= kth - SCORE_TOL)
+
+
+@pytest.mark.parametrize("N,M,d,compute,k", [
+    (1000, 700, 32, "bf16", 10), (700, 1000, 32, "bf16", 16), (333, 2050, 64, "bf16", 32),
+    (900, 600, 64, "fp8", 8), (50, 5, 16, "bf16", 8), (3, 1, 8, "bf16", 4)])
+def test_topk_lists_match_oracle(torch, lib, N, M, d, compute, k):
+    banner(f"topk {N}x{M} d={d} {compute} k={k}")
+    mk = workloads.factor_market(N, M, d, 1.0 / d, 0.5, "uint1-5", seed=N + M + k,
+                                 name="topk")
+    t = market_tensors(torch, mk)
+    with lib.Market(*t, mk.sigma, tol=1e-8, max_sweeps=200, compute=compute) as h:
+        while not h.run(16):
+            pass
+        a, b, _ = h.read()
+        lists = [h.topk(k, side) for side in (0, 1)]
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    X = quant.packed_rows(np.concatenate([mk.U, mk.Q], 1), mk.sigma, compute)
+    Y = quant.packed_rows(np.concatenate([mk.V, mk.P], 1), mk.sigma, compute)
+    T = X @ Y.T
+    logmu = np.log(2.0) * (T + np.log2(a)[:, None] + np.log2(b)[None, :])
+    for side, (idx, score) in enumerate(lists):
+        ref = logmu if side == 0 else logmu.T
+        check_lists(idx.cpu().numpy(), score.cpu().numpy(), ref, k)
+
+
+def test_topk_full_width_sampled(torch, lib):
+    """N = M = 200,000 (grid of many splits): sampled rows against the oracle."""
+    banner("topk 200k sampled rows")
+    mk = workloads.config_market(3, N=200_000, M=200_000)
+    t = market_tensors(torch, mk)
+    with lib.Market(*t, mk.sigma, max_sweeps=3) as h:
+        h.run(10)
+        a, b, _ = h.read()
+        idx, score = h.topk(10, 0)
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    rows = np.random.default_rng(3).choice(mk.N, 48, replace=False)
+    X = quant.packed_rows(np.concatenate([mk.U[rows], mk.Q[rows]], 1), mk.sigma, "bf16")
+    Y = quant.packed_rows(np.concatenate([mk.V, mk.P], 1), mk.sigma, "bf16")
+    logmu = np.log(2.0) * (X @ Y.T + np.log2(a[rows])[:, None] + np.log2(b)[None, :])
+    check_lists(idx.cpu().numpy()[rows], score.cpu().numpy()[rows], logmu, 10)

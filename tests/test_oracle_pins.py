@@ -369,3 +369,22 @@ def test_packed_rows_reduce_to_plain_rounding_and_log2_kernel():
         K = ipfp.kernel_matrix(X.astype(np.float64) @ Y.astype(np.float64).T, sigma)
         bound = np.abs(X.astype(np.float64)) @ np.abs(Y.astype(np.float64)).T / (2 * sigma)
         assert np.all(np.abs(np.log(K2 / K)) <= 2 * 2.0 ** -8 * bound + 1e-12)
+
+
+def test_topk_matches_is_repeated_selection():
+    """Sec. 4.1: recommendation = the partners of largest mu. Pinned against a
+    plain selection loop (take the largest remaining, lowest index on ties)."""
+    rng = np.random.default_rng(7)
+    L = rng.integers(0, 4, size=(6, 9)).astype(float)   # many exact ties
+    L[2, :] = -np.inf
+    for k in (1, 3, 9, 12):
+        idx, val = ipfp.topk_matches(L, k)
+        for r in range(L.shape[0]):
+            left = list(range(L.shape[1]))
+            for j in range(k):
+                if j >= L.shape[1]:
+                    assert idx[r, j] == -1 and val[r, j] == -np.inf
+                    continue
+                best = max(left, key=lambda c: (L[r, c], -c))
+                left.remove(best)
+                assert idx[r, j] == best and val[r, j] == L[r, best]
