@@ -167,6 +167,36 @@ def run_serving(torch, L, count=512, rate_hz=200.0):
             "rounds": st["rounds"], "arena_peak_bytes": st["arena_peak"]}
 
 
+def run_paper_sweeps(torch, L, sweeps=100):
+    """The timing study's shapes (Sec. 4.2): N = M from 1e2 to 1e6 with D = 50
+    factors per side, and D from 10 to 100 at N = M = 1e5; U[0, 1/sqrt(D)]
+    factors, n = 1, m = N / M, beta = 1, a fixed number of loops. Mean ms per
+    loop (one sweep) for the fused BF16 path, and for the plain FP32 path where
+    K fits. Context only: the paper's own times are on other hardware."""
+    rows = []
+
+    def one(N, D):
+        mk = workloads.paper_uniform(N, N, D)
+        t = factor_tensors(torch, mk)
+        rec = {"N": N, "M": N, "D": D, "sweeps": sweeps}
+        for path, compute in (("fused", "bf16"), ("plain", "f32")):
+            if path == "plain" and N > 100_000:
+                continue
+            L.solve_market(*t, mk.sigma, max_sweeps=2, path=path, compute=compute)
+            _, _, info = L.solve_market(*t, mk.sigma, max_sweeps=sweeps, path=path,
+                                        compute=compute, use_graph=True, check_every=sweeps)
+            rec[f"{path}_{compute}_ms_per_loop"] = info.loop_ms / (sweeps + 1)
+            rec[f"{path}_{compute}_setup_ms"] = info.setup_ms
+        log(f"paper sweep {rec}")
+        rows.append(rec)
+
+    for N in (100, 1000, 10_000, 100_000, 1_000_000):
+        one(N, 50)
+    for D in (10, 20, 100):
+        one(100_000, D)
+    return rows
+
+
 def cpu_baseline(mk, budget_s=15.0):
     """The oracle's mini-batch half-step (FP64 GEMM + exp + matvec) on row
     blocks of the default workload, timed on the host until ~budget_s."""
@@ -198,6 +228,8 @@ def main():
     ap.add_argument("--size", type=int, default=1_000_000,
                     help="N = M of the default workload (1e6 unless testing)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--paper", action="store_true",
+                    help="run only the timing study's size and D sweeps (context)")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving mix (testing)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -219,6 +251,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.paper:
+        print(json.dumps({"paper_sweeps": run_paper_sweeps(torch, L)}), flush=True)
+        return
     if args.serve_only:
         print(json.dumps({"serving": run_serving(torch, L)}), flush=True)
         return

@@ -158,7 +158,18 @@ int ipfp_footprint(const ipfp_market *mk, const ipfp_options *opt,
 int ipfp_solve_market(ipfp_ctx *ctx, const ipfp_market *mk,
                       const ipfp_options *opt, ipfp_result *res, void *stream);
 
-/* Solve a market given by a dense surplus Phi (N x M device matrix, dtype
+/* Autotuner for the fused path: times whole sweeps of this market (opened on
+ * scratch memory, then freed) for 256 and 512 output rows per workgroup and
+ * for the automatic reduction-split count, its half and its double, and
+ * returns *opt with the fastest tile_rows and splits in *best (splits 0 =
+ * automatic) and that sweep time in *best_ms (may be NULL). Results of a
+ * solve depend on the choice only through the split count, to rounding
+ * (bitwise reproducible for a fixed choice). Callers cache the choice per
+ * market shape; the Python binding keeps a JSON cache. */
+int ipfp_tune(ipfp_ctx *ctx, const ipfp_market *mk, const ipfp_options *opt,
+              ipfp_options *best, double *best_ms, void *stream);
+
+/* Solve a market given by a dense surplus Phi/* Solve a market given by a dense surplus Phi (N x M device matrix, dtype
  * F32 or F64, row stride ld_phi): batch IPFP of eq. 7 / Alg. 1 on the plain
  * path. opt->path is ignored; opt->compute chooses F32 or F64 storage of K. */
 int ipfp_solve_market_phi(ipfp_ctx *ctx, int64_t N, int64_t M,

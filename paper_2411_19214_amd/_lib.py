@@ -113,6 +113,9 @@ SIGNATURES = {
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "ipfp_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Market),
+                                 ctypes.POINTER(Options), ctypes.POINTER(Options),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "ipfp_stable_factors": (ctypes.c_int, [
         ctypes.c_void_p, ctypes.POINTER(Market), ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),

@@ -499,6 +499,61 @@ int ipfp_solve_market(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* 
   return rc;
 }
 
+int ipfp_tune(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* opt,
+              ipfp_options* best, double* best_ms, void* stream) {
+  if (!ctx || !mk || !opt || !best) return IPFP_EINVAL;
+  if (opt->path != IPFP_PATH_FUSED) return IPFP_EINVAL;
+  int rc = validate_market(mk, opt, true);
+  if (rc != IPFP_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  // candidates: 256 or 512 output rows per workgroup, times the automatic
+  // split count and its half and double (0 = automatic per pass)
+  std::vector<std::pair<int, int>> cand;
+  for (int tr : {512, 256}) {
+    const int rows = fused_rows_per_wg(fused_kpad(mk->d, opt->compute), opt->compute, tr);
+    const int sa = fused_auto_splits(mk->N, mk->M, rows);
+    cand.push_back({tr, 0});
+    if (sa / 2 >= 1) cand.push_back({tr, sa / 2});
+    if (sa * 2 <= 256) cand.push_back({tr, sa * 2});
+  }
+  const int kWarm = 1, kReps = 2;
+  double best_t = INFINITY;
+  ipfp_options win = *opt;
+  for (const auto& c : cand) {
+    ipfp_options o = *opt;
+    o.tile_rows = c.first;
+    o.splits = c.second;
+    o.tol = 0.0;
+    o.max_sweeps = kWarm + kReps + 1;
+    o.check_every = kWarm + kReps + 1;
+    o.use_graph = 0;
+    o.time_passes = 0;
+    o.b0 = opt->b0;
+    ipfp_handle* h = nullptr;
+    rc = open_impl(ctx, mk, &o, nullptr, IPFP_F32, 0, &h, s);
+    if (rc == IPFP_EBUDGET) continue;   // a candidate that does not fit is skipped
+    if (rc != IPFP_OK) return rc;
+    int done = 0;
+    rc = run_impl(h, kWarm, &done, s);
+    const double before = h->loop_ms;
+    if (rc == IPFP_OK) rc = run_impl(h, kReps, &done, s);
+    const double t = (h->loop_ms - before) / kReps;
+    destroy_handle(h);
+    if (rc != IPFP_OK) return rc;
+    if (t < best_t) {
+      best_t = t;
+      win.tile_rows = c.first;
+      win.splits = c.second;
+    }
+  }
+  if (!(best_t < INFINITY)) return IPFP_EBUDGET;
+  *best = *opt;
+  best->tile_rows = win.tile_rows;
+  best->splits = win.splits;
+  if (best_ms) *best_ms = best_t;
+  return IPFP_OK;
+}
+
 int ipfp_solve_market_phi(ipfp_ctx* ctx, int64_t N, int64_t M, ipfp_dtype phi_dtype,
                           const void* Phi, int64_t ld_phi, const double* n,
                           const double* m, double sigma, const ipfp_options* opt,

@@ -1,0 +1,78 @@
+"""Tile and split choice for the fused path, cached per market shape.
+
+``ipfp_tune`` (the C ABI) times whole sweeps of a market for each candidate
+workgroup height and reduction-split count and returns the fastest. This
+module keeps the winners in a JSON file keyed by device architecture, compute
+type, packed width and the power-of-two buckets of N and M, so that a shape is
+tuned once per machine:
+
+    opts = tuned(U, Q, V, P, n, m, sigma, compute="bf16")
+    a, b, info = solve_market(U, Q, V, P, n, m, sigma, **opts)
+
+The cache file is ``$IPFP_TUNE_CACHE`` or ``~/.cache/ipfp/tune.json``.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import math
+import os
+
+from . import _lib
+
+
+def cache_path() -> str:
+    return os.environ.get("IPFP_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "ipfp", "tune.json"))
+
+
+def _bucket(x: int) -> int:
+    return 1 << max(0, round(math.log2(max(1, x))))
+
+
+def shape_key(arch: str, compute: str, d: int, N: int, M: int) -> str:
+    kpad = (2 * d + 63) // 64 * 64 if compute == "fp8" else (2 * d + 31) // 32 * 32
+    return f"{arch}|{compute}|k{kpad}|N{_bucket(N)}|M{_bucket(M)}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, table):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tuned(U, Q, V, P, n, m, sigma, compute="bf16", path=None, refresh=False,
+          stream=None, ctx=None) -> dict:
+    """{"tile_rows": ..., "splits": ...} for this market's shape, from the cache
+    or measured on the device (``ipfp_tune``) and then cached."""
+    from . import Context, _check, _market_struct, _options, _stream_ptr, library
+    import torch
+    path = path or cache_path()
+    arch = torch.cuda.get_device_properties(U.device).gcnArchName.split(":")[0]
+    key = shape_key(arch, compute, U.shape[1], U.shape[0], V.shape[0])
+    table = _load(path)
+    if not refresh and key in table:
+        return dict(table[key]["options"])
+    mk = _market_struct(U, Q, V, P, n, m, sigma)
+    opt = _options("fused", compute, 0.0, 4, 4, 0, 0, None, False, False)
+    best = _lib.Options()
+    ms = ctypes.c_double()
+    ctx = ctx or Context.default(U.device.index or 0)
+    _check(library().ipfp_tune(ctx.handle, ctypes.byref(mk), ctypes.byref(opt),
+                               ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)),
+           "ipfp_tune")
+    choice = {"tile_rows": best.tile_rows, "splits": best.splits}
+    table = _load(path)
+    table[key] = {"options": choice, "sweep_ms": ms.value}
+    _store(path, table)
+    return choice

@@ -140,3 +140,15 @@ def test_clock_is_monotonic_ms(lib):
     t = time.monotonic() * 1e3
     b = lib.ipfp_clock_ms()
     assert a <= t + 1.0 and t <= b + 1.0 and b >= a
+
+
+def test_tune_cache_keys_and_roundtrip(tmp_path):
+    from paper_2411_19214_amd import tune
+    k1 = tune.shape_key("gfx950", "bf16", 64, 1_000_000, 1_000_000)
+    assert k1 == "gfx950|bf16|k128|N1048576|M1048576"
+    assert tune.shape_key("gfx950", "fp8", 32, 700, 1500) == "gfx950|fp8|k64|N512|M2048"
+    assert tune.shape_key("gfx950", "bf16", 40, 3, 1) == "gfx950|bf16|k96|N4|M1"
+    path = str(tmp_path / "sub" / "tune.json")
+    assert tune._load(path) == {}
+    tune._store(path, {k1: {"options": {"tile_rows": 512, "splits": 0}}})
+    assert tune._load(path)[k1]["options"] == {"tile_rows": 512, "splits": 0}

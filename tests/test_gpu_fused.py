@@ -225,3 +225,19 @@ def test_mu_pairs(torch, lib):
     assert rel_err(mu, want) < 1e-13
     with pytest.raises(lib.IPFPError):
         lib.mu_pairs(U, Q, V, P, mk.sigma, a, b, torch.tensor([50]), torch.tensor([0]))
+
+
+def test_autotuner_choice_and_cache(torch, lib, tmp_path):
+    banner("autotuner 20k x 12k d=32")
+    from paper_2411_19214_amd import tune
+    mk = workloads.config_market(2, N=20000, M=12000)
+    t = market_tensors(torch, mk)
+    path = str(tmp_path / "tune.json")
+    opts = tune.tuned(*t, mk.sigma, compute="bf16", path=path)
+    assert opts["tile_rows"] in (256, 512) and 0 <= opts["splits"] <= 256
+    assert tune.tuned(*t, mk.sigma, compute="bf16", path=path) == opts   # cached
+    a0, b0, i0 = lib.solve_market(*t, mk.sigma, max_sweeps=30)
+    a1, b1, i1 = lib.solve_market(*t, mk.sigma, max_sweeps=30, **opts)
+    # the split count only reorders FP64 partial sums
+    assert rel_err(a1.cpu().numpy(), a0.cpu().numpy()) < 1e-10
+    assert rel_err(b1.cpu().numpy(), b0.cpu().numpy()) < 1e-10
