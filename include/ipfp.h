@@ -237,6 +237,34 @@ int ipfp_stable_factors(ipfp_ctx *ctx, const ipfp_market *mk, const double *a,
 int ipfp_market_topk(ipfp_handle *h, int side, int32_t k, int32_t *idx_out,
                      float *score_out, void *stream);
 
+/* Gradient of the optimal welfare with respect to the factors (Sec. 5 names
+ * back-propagation into the recommender as future work). At the optimum of
+ * eq. 2-3, dW/dPhi_xy = mu_xy (envelope theorem), and Phi = [U|Q][V|P]^T
+ * (eq. 8), so side 0 gives G = mu [V|P] = [dW/dU | dW/dQ] (N x 2d) and side
+ * 1 gives G = mu^T [U|Q] = [dW/dV | dW/dP] (M x 2d). Computed for a resident
+ * fused BF16 market at its current state, from the operands the solve uses:
+ * mu = 2^T a b with T from the packed rows, and the packed rows divided by
+ * their prescale as the factor values (the factors as the matrix cores see
+ * them). g_out: rows x 2d FP64 device, row stride ld_g >= 2d. Scratch of
+ * splits x rows x kpad doubles is allocated for the call and charged to the
+ * context budget. IPFP_EINVAL for the plain path or FP8 operands. */
+int ipfp_market_gradient(ipfp_handle *h, int side, double *g_out, int64_t ld_g,
+                         void *stream);
+
+/* The fused path's packed operand of one side/* The fused path's packed operand of one side/* Gradient of the optimal welfare with respect to the factors (Sec. 5 names
+ * back-propagation into the recommender as future work). At the optimum of
+ * eq. 2-3, dW/dPhi_xy = mu_xy (envelope theorem), and Phi = [U|Q][V|P]^T
+ * (eq. 8), so side 0 gives G = mu [V|P] = [dW/dU | dW/dQ] (N x 2d) and side
+ * 1 gives G = mu^T [U|Q] = [dW/dV | dW/dP] (M x 2d). Computed for a resident
+ * fused BF16 market at its current state, from the operands the solve uses:
+ * mu = 2^T a b with T from the packed rows, and the packed rows divided by
+ * their prescale as the factor values (the factors as the matrix cores see
+ * them). g_out: rows x 2d FP64 device, row stride ld_g >= 2d. Scratch of
+ * splits x rows x kpad doubles is allocated for the call and charged to the
+ * context budget. IPFP_EINVAL for the plain path or FP8 operands. */
+int ipfp_market_gradient(ipfp_handle *h, int side, double *g_out, int64_t ld_g,
+                         void *stream);
+
 /* The fused path's packed operand of one side/* The fused path's packed operand of one side (Sec. 3.3's factor matrices as
  * the matrix cores read them): rows p [A|B] concatenated, zero-padded to
  * `kpad` columns and rounded to `compute`, where p = sqrt(log2(e)/(2 sigma))

@@ -29,7 +29,8 @@ suite. ``ipfp_minibatch`` and ``half_step_rows`` are pinned against
 ``ipfp_batch`` (the paper states the mini-batch form is exact) and against the
 closed forms. ``stable_factors`` is pinned against log(mu) of ``matching``.
 ``topk_matches`` is pinned against a selection loop that repeatedly takes the
-largest remaining entry.
+largest remaining entry; ``welfare_gradient`` against central differences of
+the optimal welfare computed by the IPFP-free primal Newton solve.
 """
 from __future__ import annotations
 
@@ -236,6 +237,20 @@ def stable_factors(U, Q, V, P, a, b, sigma: float):
     xi = np.concatenate([np.asarray(V, np.float64), np.asarray(P, np.float64),
                          np.ones((M, 1)), (2.0 * sigma * np.log(b))[:, None]], 1)
     return psi, xi
+
+
+def welfare_gradient(K, a, b, X, Y):
+    """Gradient of the optimal welfare with respect to the factors (the
+    back-propagation into the recommender that Sec. 5 names as future work).
+
+    At the optimum of eq. 2-3 the envelope theorem gives dW*/dPhi_xy = mu_xy
+    (the entropy term does not depend on Phi), and Phi = X Y^T with X = [U|Q],
+    Y = [V|P] (eq. 8), so dW*/dX = mu Y and dW*/dY = mu^T X, with
+    mu = K_xy a_x b_y (eq. 4). Returns (G_X, G_Y) in FP64."""
+    mu = matching(K, a, b)
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    return mu @ Y, mu.T @ X
 
 
 def topk_matches(logmu, k: int):

@@ -287,6 +287,18 @@ class Market:
                "ipfp_market_topk")
         return idx, score
 
+    def gradient(self, side: int = 0):
+        """dW/d[U|Q] (side 0, N x 2d) or dW/d[V|P] (side 1, M x 2d) at the
+        current state, FP64 (``ipfp_market_gradient``)."""
+        torch = _torch()
+        rows = self._mk.N if side == 0 else self._mk.M
+        w = 2 * self._mk.d
+        g = torch.empty((rows, w), dtype=torch.float64, device=self.device)
+        _check(library().ipfp_market_gradient(self.handle, int(side), g.data_ptr(), w,
+                                              _stream_ptr(self.stream)),
+               "ipfp_market_gradient")
+        return g
+
     def close(self):
         if getattr(self, "handle", None):
             library().ipfp_market_close(self.handle)

@@ -121,6 +121,8 @@ SIGNATURES = {
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "ipfp_market_topk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ipfp_market_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                            ctypes.c_int64, ctypes.c_void_p]),
     "ipfp_default_server_options": (None, [ctypes.POINTER(ServerOptions)]),
     "ipfp_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerOptions),
                                           ctypes.POINTER(ctypes.c_void_p)]),

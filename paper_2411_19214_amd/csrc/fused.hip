@@ -802,6 +802,264 @@ hipError_t launch_topk(const FusedPass& fp, const double* a_out, int k, int spli
 #undef IPFP_TOPK_CASE
 }
 
+// ---- welfare gradient with respect to the factors ------------------------------
+//
+// dW*/dPhi = mu at the optimum (envelope theorem on eq. 2-3), so with
+// Phi = X Y^T (eq. 8) the gradient of the output side is G_o = sum_r mu_or Y_r
+// = a_o 2^(E - h_o) / p * sum_r P_or Ypk_r with P_or = 2^(T_or + h_o) w~_r
+// (the reduction pass's terms) and Ypk = p Y the packed value rows. The pass
+// is the reduction pass followed by a second product on the matrix cores
+// (flash-attention-forward shape): the 32 x 32 tile of P, split into BF16
+// high and low parts (about 16 significant bits together), times the staged
+// value tile. The value tile is staged a second time in LDS transposed
+// (columns contiguous, rows padded by 8 bytes against bank conflicts), so a
+// lane reads its eight K values as two 8-byte loads. The product's K order is
+// a permutation of the 32 reduced rows of a subtile that lets every lane feed
+// its own P values as the B operand. FP32 accumulators are folded into FP64
+// after every stage, in registers for packed rows up to 128 columns and in
+// the lane's own slots of the partial buffer (every fourth stage) above that;
+// one FP64 partial per (split, row, column) results.
+template <int KP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+    k_grad_pass(const uint8_t* __restrict__ Xo, const uint8_t* __restrict__ Yr,
+                const double* __restrict__ wred, const int* __restrict__ Eptr,
+                const float* __restrict__ shift, int R, int L, int tiles_per_split,
+                int nsplit, double* __restrict__ gpart) {
+  constexpr int WAVES = 4;
+  typedef PassCore<KP, 1, WAVES, false> C;
+  typedef typename C::Frag Frag;
+  typedef Op<false> O;
+  constexpr int RB = C::RB, kTY = C::kTY, NS = C::NS, LS = C::LS, NT = C::NT;
+  constexpr int CH = C::CH, CPT = C::CPT, SUB = C::SUB;
+  constexpr int NB = KP / 32;              // 32-column blocks of the value rows
+  constexpr int TS = kTY * 2 + 8;          // bytes per transposed (column) row
+  __shared__ __attribute__((aligned(16))) uint8_t ys[2][kTY * LS];
+  __shared__ __attribute__((aligned(16))) uint8_t yt[2][KP * TS];
+  __shared__ __attribute__((aligned(16))) float ws[2][kTY];
+
+  int E = *Eptr;
+  if (E == INT_MIN) E = 0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int split = blockIdx.x % nsplit, rb = blockIdx.x / nsplit;
+  const int T = (L + kTY - 1) / kTY;
+  const int t0 = split * tiles_per_split, t1 = min(T, t0 + tiles_per_split);
+  const int x = (rb * WAVES + wave) * 32 + l32;
+  const bool ok = x < R;
+
+  Frag bfrag[NS];
+  {
+    const uint8_t* src = Xo + (int64_t)(ok ? x : 0) * RB + h * O::SB;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      Frag f = lds_frag<false, Frag>(src, s);
+      if (!ok) *reinterpret_cast<intx4*>(&f) = intx4{0, 0, 0, 0};
+      bfrag[s] = f;
+    }
+  }
+  const float hv = ok ? shift[x] : 0.f;
+  constexpr bool kRegs = KP <= 128;        // FP64 sums in registers
+  constexpr int kG = kRegs ? 1 : 16;       // FP64 slots when kept in memory
+  floatx16 g32[NB];
+  double g64[kRegs ? NB : 1][kRegs ? 16 : 1];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) g32[nb][j] = 0.f;
+  if constexpr (kRegs) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) g64[nb][j] = 0.0;
+  }
+  (void)kG;
+  double* dst = gpart + ((int64_t)split * R + (ok ? x : 0)) * KP;
+  bool first = true;
+
+  intx4 pre[CPT];
+  float pw = 0.f;
+  auto gload = [&](int tile) {
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int chunk = min(tid + q * NT, CH - 1);
+      const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
+      const uint32_t y = (uint32_t)min(tile * kTY + r, L - 1);
+      pre[q] = *reinterpret_cast<const intx4*>(Yr + cb * 16 + (uint64_t)y * RB);
+    }
+    const int y = tile * kTY + (tid % kTY);
+    pw = y < L ? (float)ldexp(wred[min(y, L - 1)], -E) : 0.f;
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int chunk = min(tid + q * NT, CH - 1);
+      const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
+      *reinterpret_cast<intx4*>(&ys[buf][r * LS + cb * 16]) = pre[q];
+      // transposed copy: element c = 8 cb + i of row r to yt[c][r]
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const uint32_t word = (uint32_t)pre[q][i >> 1];
+        *reinterpret_cast<uint16_t*>(&yt[buf][(cb * 8 + i) * TS + r * 2]) =
+            (uint16_t)(word >> (16 * (i & 1)));
+      }
+    }
+    ws[buf][tid % kTY] = pw;
+  };
+
+  if (t0 < t1) {
+    gload(t0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int tile = t0; tile < t1; ++tile) {
+    const int buf = (tile - t0) & 1;
+    gload(min(tile + 1, t1 - 1));
+#pragma unroll
+    for (int sub = 0; sub < SUB; ++sub) {
+      const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
+      floatx16 acc;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] = hv;
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        acc = mfma_step<false>(lds_frag<false, Frag>(arow, s), bfrag[s], acc, 127, 127);
+      float p[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int yr = sub * 32 + 8 * (j >> 2) + 4 * h + (j & 3);
+        p[j] = __builtin_amdgcn_exp2f(acc[j]) * ws[buf][yr];
+      }
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        // B operand: this lane's P at K slots 8h..8h+7 (reduced rows
+        // 16 ks + 8 (i / 4) + 4 h + i % 4), high and low BF16 parts
+        uint16_t hi[8], lo[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float v = p[8 * ks + i];
+          hi[i] = bf16_rne(v);
+          lo[i] = bf16_rne(v - __uint_as_float((uint32_t)hi[i] << 16));
+        }
+        bf16x8 bh, bl;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          reinterpret_cast<uint16_t*>(&bh)[i] = hi[i];
+          reinterpret_cast<uint16_t*>(&bl)[i] = lo[i];
+        }
+        const int r0 = sub * 32 + 16 * ks + 4 * h;   // rows r0..r0+3, r0+8..r0+11
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          // A operand: value column 32 nb + l32 at the same eight rows
+          const uint8_t* col = &yt[buf][(32 * nb + l32) * TS];
+          intx4 av;
+          const int2 v0 = *reinterpret_cast<const int2*>(col + r0 * 2);
+          const int2 v1 = *reinterpret_cast<const int2*>(col + (r0 + 8) * 2);
+          av[0] = v0.x;
+          av[1] = v0.y;
+          av[2] = v1.x;
+          av[3] = v1.y;
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&av);
+          g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, g32[nb], 0, 0, 0);
+          g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, g32[nb], 0, 0, 0);
+        }
+      }
+    }
+    // lane (o, h) holds columns 32 nb + 8 (j / 4) + 4 h + j % 4 of row o
+    if constexpr (kRegs) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          g64[nb][j] += (double)g32[nb][j];
+          g32[nb][j] = 0.f;
+        }
+    } else if (((tile - t0) & 3) == 3 || tile == t1 - 1) {
+      if (ok) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            double* slot = dst + 32 * nb + 8 * (j >> 2) + 4 * h + (j & 3);
+            *slot = (first ? 0.0 : *slot) + (double)g32[nb][j];
+          }
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) g32[nb][j] = 0.f;
+      first = false;
+    }
+    lstore(buf ^ 1);
+    __syncthreads();
+  }
+  if (ok) {
+    if constexpr (kRegs) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dst[32 * nb + 8 * (j >> 2) + 4 * h + (j & 3)] = g64[nb][j];
+    } else if (first) {   // a split with no tiles
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dst[32 * nb + 8 * (j >> 2) + 4 * h + (j & 3)] = 0.0;
+    }
+  }
+}
+
+// G_o,c = a_o 2^(E - h_o) / p * sum over splits (fixed order), columns c < 2d.
+__global__ void __launch_bounds__(256)
+    k_grad_combine(const double* __restrict__ gpart, int nsplit, int R, int kpad, int width,
+                   const int* __restrict__ Eptr, const float* __restrict__ shift,
+                   const double* __restrict__ a_out, double inv_p, double* __restrict__ g,
+                   int64_t ld_g) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)R * width) return;
+  const int o = (int)(i / width), c = (int)(i % width);
+  int E = *Eptr;
+  if (E == INT_MIN) E = 0;
+  double sum = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) sum += gpart[((int64_t)sp * R + o) * kpad + c];
+  g[(int64_t)o * ld_g + c] = sum * exp2((double)E - (double)shift[o]) * a_out[o] * inv_p;
+}
+
+template <int KP>
+static hipError_t grad_t(const FusedPass& fp, const int* Eptr, const double* a_out, double inv_p,
+                         int splits, double* gpart, int width, double* g, int64_t ld_g,
+                         hipStream_t s) {
+  constexpr int kTY = ty_for(KP * 2);
+  const int64_t rblocks = (fp.out.rows + 127) / 128;
+  const int T = (int)((fp.red.rows + kTY - 1) / kTY);
+  const int tps = (T + splits - 1) / splits;
+  hipLaunchKernelGGL((k_grad_pass<KP>), dim3((unsigned)(rblocks * splits)), dim3(256), 0, s,
+                     (const uint8_t*)fp.out.ops, (const uint8_t*)fp.red.ops, fp.w_red, Eptr,
+                     fp.shift, (int)fp.out.rows, (int)fp.red.rows, tps, splits, gpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = fp.out.rows * width;
+  hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, gpart,
+                     splits, (int)fp.out.rows, (int)fp.kpad, width, Eptr, fp.shift, a_out,
+                     inv_p, g, ld_g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gradient(const FusedPass& fp, const int* Eptr, const double* a_out,
+                           double inv_p, int splits, double* gpart, int width, double* g,
+                           int64_t ld_g, hipStream_t s) {
+  if (fp.compute != IPFP_BF16) return hipErrorInvalidValue;
+  switch (fp.kpad) {
+    case 32: return grad_t<32>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
+    case 64: return grad_t<64>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
+    case 96: return grad_t<96>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
+    case 128: return grad_t<128>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
+    case 160: return grad_t<160>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
+    case 192: return grad_t<192>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
+    case 224: return grad_t<224>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
+    case 256: return grad_t<256>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // ---- combine partial sums, update scalings -----------------------------------
 
 // Finishes output row o given lS = log2((K w)_o): the residual of the current

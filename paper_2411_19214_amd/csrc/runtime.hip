@@ -663,6 +663,50 @@ int ipfp_market_topk(ipfp_handle* h, int side, int32_t k, int32_t* idx_out, floa
   return rc;
 }
 
+int ipfp_market_gradient(ipfp_handle* h, int side, double* g_out, int64_t ld_g,
+                         void* stream) {
+  if (!h || h->plain || (side != 0 && side != 1) || !g_out) return IPFP_EINVAL;
+  if (h->opt.compute != IPFP_BF16) return IPFP_EINVAL;
+  const int width = (int)(2 * h->mk.d);
+  if (ld_g < width) return IPFP_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return IPFP_EHIP;
+  int rc = read_ctl(h, s);
+  if (rc != IPFP_OK) return rc;
+  const Ctl c = *h->host_ctl;
+  const int state = c.done ? c.stop_sweep : c.sweep;
+  const double* u = h->u2 + (int64_t)(state & 1) * h->N;
+  FusedPass fp = side == 0 ? h->rowp : h->colp;
+  fp.w_red = side == 0 ? h->v : u;
+  fp.red_dbuf = 0;
+  const double* a_out = side == 0 ? u : h->v;
+  const int64_t R = fp.out.rows, L = fp.red.rows;
+  int splits = fused_auto_splits(R, L, 128);
+  while (splits > 1 && (size_t)splits * R * h->kpad * sizeof(double) > ((size_t)2 << 30))
+    splits /= 2;
+  const size_t part = (size_t)splits * R * h->kpad * sizeof(double);
+  const size_t bytes = align_up(sizeof(Ctl), 256) + part;
+  rc = ctx_reserve(h->ctx, bytes);
+  if (rc != IPFP_OK) return rc;
+  char* mem = nullptr;
+  if (hipMalloc((void**)&mem, bytes) != hipSuccess) {
+    ctx_release(h->ctx, bytes);
+    return IPFP_EBUDGET;
+  }
+  Ctl* sc = (Ctl*)mem;
+  double* gpart = (double*)(mem + align_up(sizeof(Ctl), 256));
+  const double inv_p = 1.0 / (double)fused_prescale(h->mk.sigma);
+  rc = IPFP_OK;
+  if (launch_init_exp(fp.w_red, L, sc, 0, s) != hipSuccess ||
+      launch_gradient(fp, &sc->wexp[0], a_out, inv_p, splits, gpart, width, g_out, ld_g, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = IPFP_EHIP;
+  (void)hipFree(mem);
+  ctx_release(h->ctx, bytes);
+  return rc;
+}
+
 int ipfp_pack_side(ipfp_ctx* ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
                    const void* A, const void* B, int64_t ld, ipfp_dtype compute,
                    double sigma, void* out, float* scale_out, int64_t* kpad_out,

@@ -1,5 +1,6 @@
 """GPU tests of the solve's outputs beyond (a, b): the stable factors of
-eq. 11 and the top-k recommendation lists ranked by the stable matching.
+eq. 11, the top-k recommendation lists ranked by the stable matching, and the
+gradient of the optimal welfare with respect to the factors.
 
 Top-k is an integer decision taken from floating-point scores, and near-ties
 may order differently in the kernel's FP32 and the oracle's FP64. The oracle
@@ -107,3 +108,38 @@ def test_topk_full_width_sampled(torch, lib):
     Y = quant.packed_rows(np.concatenate([mk.V, mk.P], 1), mk.sigma, "bf16")
     logmu = np.log(2.0) * (X @ Y.T + np.log2(a[rows])[:, None] + np.log2(b)[None, :])
     check_lists(idx.cpu().numpy()[rows], score.cpu().numpy()[rows], logmu, 10)
+
+
+@pytest.mark.parametrize("N,M,d", [(1000, 700, 32), (333, 2050, 64), (257, 20000, 32),
+                                   (130, 90, 50), (64, 70, 100), (100, 41, 128)])
+def test_gradient_matches_oracle(torch, lib, N, M, d):
+    """G = mu [V|P] and mu^T [U|Q] (envelope theorem) against the oracle on
+    the same packed operands. Bound per component, from the arithmetic: P in
+    two BF16 parts (relative 2^-18), FP32 products accumulated over one stage
+    of at most 128 rows (128 x 2^-24) and folded into FP64, so
+    |G - G_ref| <= 2e-5 sum_y mu_xy |Y_y|."""
+    banner(f"gradient {N}x{M} d={d}")
+    mk = workloads.factor_market(N, M, d, 1.0 / d, 0.7, "uint1-5", seed=N * 7 + M + d,
+                                 name="grad")
+    t = market_tensors(torch, mk)
+    with lib.Market(*t, mk.sigma, tol=1e-9, max_sweeps=300) as h:
+        while not h.run(16):
+            pass
+        a, b, _ = h.read()
+        gx = h.gradient(0).cpu().numpy()
+        gy = h.gradient(1).cpu().numpy()
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    p = float(quant.prescale(mk.sigma))
+    X = quant.packed_rows(np.concatenate([mk.U, mk.Q], 1), mk.sigma, "bf16")
+    Y = quant.packed_rows(np.concatenate([mk.V, mk.P], 1), mk.sigma, "bf16")
+    K = O.kernel_from_log2(X @ Y.T)
+    GX, GY = O.welfare_gradient(K, a, b, X / p, Y / p)
+    mu = O.matching(K, a, b)
+    bx = mu @ np.abs(Y / p)
+    by = mu.T @ np.abs(X / p)
+    ex = np.max(np.abs(gx - GX) / bx)
+    ey = np.max(np.abs(gy - GY) / by)
+    print(f"gradient {N}x{M} d={d}: max |err| / sum mu|Y| = {ex:.2e} (rows), {ey:.2e} (cols)",
+          flush=True)
+    assert gx.shape == (N, 2 * d) and gy.shape == (M, 2 * d)
+    assert ex < 2e-5 and ey < 2e-5

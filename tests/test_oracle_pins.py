@@ -388,3 +388,32 @@ def test_topk_matches_is_repeated_selection():
                 best = max(left, key=lambda c: (L[r, c], -c))
                 left.remove(best)
                 assert idx[r, j] == best and val[r, j] == L[r, best]
+
+
+def test_welfare_gradient_is_derivative_of_optimal_welfare():
+    """Envelope theorem, checked without IPFP: central differences of the
+    primal optimum W*(X, Y) (damped Newton on eq. 2-3) against mu Y, mu^T X."""
+    rng = np.random.default_rng(11)
+    N, M, d, beta = 3, 4, 2, 0.7
+    U, Q = rng.normal(0, 0.6, (N, d)), rng.normal(0, 0.6, (N, d))
+    V, P = rng.normal(0, 0.6, (M, d)), rng.normal(0, 0.6, (M, d))
+    n, m = rng.uniform(0.5, 2.0, N), rng.uniform(0.5, 2.0, M)
+    X, Y = np.concatenate([U, Q], 1), np.concatenate([V, P], 1)
+
+    def wstar(X_, Y_):
+        return brute.primal_newton(X_ @ Y_.T, n, m, beta).value
+
+    K = ipfp.kernel_matrix(X @ Y.T, beta)
+    r = ipfp.ipfp_batch(K, n, m, tol=1e-15, max_sweeps=5000)
+    GX, GY = ipfp.welfare_gradient(K, r.a, r.b, X, Y)
+    eps = 1e-5
+    for (i, j) in [(0, 0), (1, 3), (2, 1)]:
+        E = np.zeros_like(X)
+        E[i, j] = eps
+        fd = (wstar(X + E, Y) - wstar(X - E, Y)) / (2 * eps)
+        assert abs(fd - GX[i, j]) < 1e-6 * max(1.0, abs(fd)), (i, j, fd, GX[i, j])
+    for (i, j) in [(0, 2), (3, 0)]:
+        E = np.zeros_like(Y)
+        E[i, j] = eps
+        fd = (wstar(X, Y + E) - wstar(X, Y - E)) / (2 * eps)
+        assert abs(fd - GY[i, j]) < 1e-6 * max(1.0, abs(fd)), (i, j, fd, GY[i, j])
