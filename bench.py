@@ -123,7 +123,7 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else None
 
 
-def run_serving(torch, L, count=512, rate_hz=200.0):
+def run_serving(torch, L, count=512, rate_hz=200.0, aging_ms=0.0, lane_blocks=0):
     """The serving mix: `count` markets (N, M log-uniform in [1e3, 2e5], d = 32,
     sigma in {0.5, 1}, unit margins, tol 1e-6) submitted at Poisson(rate)
     arrival times to one continuous-batching server; factors are generated on
@@ -132,7 +132,8 @@ def run_serving(torch, L, count=512, rate_hz=200.0):
     log(f"serving: generating {count} markets on the device")
     tens = [workloads.device_request_factors(torch, r) for r in reqs]
     torch.cuda.synchronize()
-    with L.Server(arena_bytes=16 << 30, max_active=256, lanes=3, chunk=4) as srv:
+    with L.Server(arena_bytes=16 << 30, max_active=256, lanes=3, chunk=4, aging_ms=aging_ms,
+                  lane_blocks=lane_blocks) as srv:
         # load the grouped kernels once, outside the measured window
         w = srv.submit(*workloads.device_request_factors(
             torch, workloads.Request(-1, 0.0, 1000, 1000, 32, 1.0, 1)), 1.0, tol=1e-6)
@@ -228,6 +229,10 @@ def main():
     ap.add_argument("--size", type=int, default=1_000_000,
                     help="N = M of the default workload (1e6 unless testing)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--aging-ms", type=float, default=0.0,
+                    help="serving: waiting time worth a halving of N*M (0 = library default)")
+    ap.add_argument("--lane-blocks", type=int, default=0,
+                    help="serving: workgroups per pass a lane admits up to (0 = default)")
     ap.add_argument("--paper", action="store_true",
                     help="run only the timing study's size and D sweeps (context)")
     ap.add_argument("--serve-only", action="store_true",
@@ -255,7 +260,8 @@ def main():
         print(json.dumps({"paper_sweeps": run_paper_sweeps(torch, L)}), flush=True)
         return
     if args.serve_only:
-        print(json.dumps({"serving": run_serving(torch, L)}), flush=True)
+        print(json.dumps({"serving": run_serving(torch, L, aging_ms=args.aging_ms,
+                                                 lane_blocks=args.lane_blocks)}), flush=True)
         return
     cfg = workloads.CONFIGS[3]
     log(f"generating C3 market N=M={args.size} d={cfg['d']}")

@@ -318,7 +318,7 @@ typedef struct {
                            0 = split log2(N*M) in [20, 36] evenly           */
   int32_t lane_blocks;  /* reduction workgroups per pass a lane admits up
                            to; 0 = 2048 (8 per compute unit)                */
-  double aging_ms;      /* waiting time worth a halving of N*M; 0 = 1000    */
+  double aging_ms;      /* waiting time worth a halving of N*M; 0 = 4000    */
 } ipfp_server_options;
 
 enum { IPFP_REQ_QUEUED = 0, IPFP_REQ_RUNNING = 1, IPFP_REQ_FINISHED = 2 };

@@ -733,7 +733,7 @@ void ipfp_default_server_options(ipfp_server_options* opt) {
   opt->compute = IPFP_BF16;
   opt->tile_rows = 0;
   opt->lane_blocks = 2048;
-  opt->aging_ms = 1000.0;
+  opt->aging_ms = 4000.0;
 }
 
 int ipfp_server_create(ipfp_ctx* ctx, const ipfp_server_options* opt, ipfp_server** out) {

@@ -58,6 +58,7 @@ def test_default_options(lib):
     s = _lib.ServerOptions()
     lib.ipfp_default_server_options(ctypes.byref(s))
     assert (s.max_active, s.lanes, s.chunk, s.compute) == (256, 3, 4, _lib.BF16)
+    assert (s.lane_blocks, s.aging_ms) == (2048, 4000.0)
     assert s.arena_bytes == 1 << 30
 
 
