@@ -202,10 +202,10 @@ void ipfp_market_close(ipfp_handle *h);
  * mu_out[i] = exp(Phi_{xs[i], ys[i]} / (2 sigma)) a_{xs[i]} b_{ys[i]}, where
  * Phi is formed in FP64 from the market's factors as given (in_dtype values,
  * not the packed compute operands). xs, ys: device int64 indices; a, b:
- * device FP64 scalings; mu_out: device FP64. Indices out of range give
- * IPFP_EINVAL (checked on the host before any launch is not possible for
- * device arrays: the kernel writes NaN for an out-of-range pair and the call
- * returns IPFP_EINVAL). */
+ * device FP64 scalings; mu_out: device FP64. The indices live in device
+ * memory, so they are checked by the kernel: an out-of-range pair gets NaN
+ * and the call returns IPFP_EINVAL after the stream has synchronised (the
+ * other pairs are still written). The margins of mk are not read. */
 int ipfp_mu_pairs(ipfp_ctx *ctx, const ipfp_market *mk, const double *a,
                   const double *b, const int64_t *xs, const int64_t *ys,
                   int64_t count, double *mu_out, void *stream);
