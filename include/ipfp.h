@@ -107,8 +107,9 @@ typedef struct {
   int32_t splits;        /* reduction splits per half-sweep; 0 = automatic.
                             Results are bitwise reproducible for fixed
                             splits; across splits they agree to rounding.     */
-  int32_t tile_rows;     /* FUSED: output rows per workgroup (256 or 512);
-                            0 = automatic                                     */
+  int32_t tile_rows;     /* FUSED: output rows per workgroup (128, 256 or
+                            512); 0 = a per-type default (256 for BF16 with
+                            2d = 64 and FP8 up to 2d = 128, else 512)         */
   const double *b0;      /* optional device warm start for v (length M);
                             NULL = ones. The initial u is never read.         */
   int32_t use_graph;     /* 1 = replay sweeps through a captured hipGraph     */

@@ -1341,6 +1341,17 @@ hipError_t launch_fused_shift(const FusedPass& fp, Ctl* ctl, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Default workgroup height (tile_rows = 0). Measured on MI355X at N = M = 1e6:
+// two-tile kernels that fit three waves per SIMD (BF16 with 2d = 64, FP8 up
+// to 2d = 128) run 8-16 % faster as 4-wave workgroups, three of which share a
+// compute unit, than as 8-wave ones; BF16 with 2d = 128 is 1-2 % faster with
+// 8 waves; one-tile kernels use 8 waves either way.
+int fused_default_tile_rows(int64_t kpad, ipfp_dtype compute) {
+  const bool fp8 = compute == IPFP_FP8E4M3;
+  if (fp8 ? kpad <= 128 : kpad == 64) return 256;
+  return 512;
+}
+
 int fused_rows_per_wg(int64_t kpad, ipfp_dtype compute, int tile_rows) {
   const bool fp8 = compute == IPFP_FP8E4M3;
   const int xt = xt_for((int)kpad, fp8);

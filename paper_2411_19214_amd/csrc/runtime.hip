@@ -48,7 +48,7 @@ void ipfp::handle_layout(ipfp_handle* h, Carver& cv) {
     h->yscale = cv.take<float>(M);
     h->xshift = cv.take<float>(N);
     h->yshift = cv.take<float>(M);
-    const int tr = h->opt.tile_rows > 0 ? h->opt.tile_rows : 512;
+    const int tr = h->opt.tile_rows > 0 ? h->opt.tile_rows : fused_default_tile_rows(h->kpad, cd);
     const int rx = fused_rows_per_wg(h->kpad, cd, tr);
     int sx = h->opt.splits > 0 ? h->opt.splits : fused_auto_splits(N, M, rx);
     int sy = h->opt.splits > 0 ? h->opt.splits : fused_auto_splits(M, N, rx);

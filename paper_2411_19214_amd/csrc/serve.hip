@@ -360,16 +360,18 @@ hipError_t build_table(Lane& L) {
 hipError_t enqueue_group_unit(ipfp_server* srv, Lane& L) {
   const int count = (int)L.active.size();
   const ipfp_dtype cd = srv->opt.compute;
-  const int tr = srv->opt.tile_rows > 0 ? srv->opt.tile_rows : 512;
+  auto tr = [&](int64_t kpad) {
+    return srv->opt.tile_rows > 0 ? srv->opt.tile_rows : fused_default_tile_rows(kpad, cd);
+  };
   for (const PassKey& k : L.keys)
     TRY(launch_group_pass(L.row, L.row_idx + k.idx_off, L.row_pf + k.first_off, k.cnt,
-                          k.row_total, k.kpad, cd, tr, L.s));
+                          k.row_total, k.kpad, cd, tr(k.kpad), L.s));
   TRY(launch_group_combine(L.row, L.row_cf, count, L.row_ctot, L.s));
   TRY(launch_group_fixup(L.row, count, kGroupFixupBlocks, cd, L.s));
   TRY(launch_group_check(L.chk, count, L.s));
   for (const PassKey& k : L.keys)
     TRY(launch_group_pass(L.col, L.col_idx + k.idx_off, L.col_pf + k.first_off, k.cnt,
-                          k.col_total, k.kpad, cd, tr, L.s));
+                          k.col_total, k.kpad, cd, tr(k.kpad), L.s));
   TRY(launch_group_combine(L.col, L.col_cf, count, L.col_ctot, L.s));
   return launch_group_fixup(L.col, count, kGroupFixupBlocks, cd, L.s);
 }
@@ -833,7 +835,8 @@ int ipfp_submit(ipfp_server* srv, const ipfp_market* mk, const ipfp_options* opt
   if (rc != IPFP_OK) return rc;
   if (bytes > srv->arena.cap()) return IPFP_EBUDGET;
   const int64_t kpad = fused_kpad(mk->d, o.compute);
-  const int rx = fused_rows_per_wg(kpad, o.compute, o.tile_rows > 0 ? o.tile_rows : 512);
+  const int rx = fused_rows_per_wg(
+      kpad, o.compute, o.tile_rows > 0 ? o.tile_rows : fused_default_tile_rows(kpad, o.compute));
   const int sx = o.splits > 0 ? o.splits : fused_auto_splits(mk->N, mk->M, rx);
   if (hipSetDevice(srv->ctx->device) != hipSuccess) return IPFP_EHIP;
   hipEvent_t ready = nullptr;
