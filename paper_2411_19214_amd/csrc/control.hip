@@ -1,4 +1,6 @@
-// Convergence control, small vector kernels and the matching-mass output.
+// Convergence control (single-market and grouped), small vector kernels and
+// the outputs computed from the factors as given: matching masses at pairs
+// and the stable factors.
 #include <math.h>
 
 #include "common.h"

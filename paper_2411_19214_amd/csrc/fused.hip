@@ -27,6 +27,11 @@
 // FP32 and added to an FP64 running sum. Partial sums per (split, row) are
 // combined in fixed split order in FP64, so results are bitwise reproducible
 // for a fixed split count.
+//
+// The same tile machinery serves the grouped (many-market) launches of the
+// serving layer, the recommendation lists (top-k epilogue instead of the sum)
+// and the welfare gradient (a second matrix-core product of the exp'd tile
+// with the value rows).
 #include <limits.h>
 #include <math.h>
 

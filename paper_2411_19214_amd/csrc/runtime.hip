@@ -1,7 +1,8 @@
-// C ABI: contexts, resident markets, the device-driven sweep loop and the
-// one-call solves. Every sweep is a fixed sequence of kernels on the caller's
-// stream; the only host/device synchronisation is a 64-byte read of the
-// control block after each batch of enqueued sweeps.
+// C ABI: contexts, resident markets, the device-driven sweep loop, the
+// one-call solves, the outputs (stable factors, recommendation lists,
+// gradient) and the autotuner. Every sweep is a fixed sequence of kernels on
+// the caller's stream; the only host/device synchronisation is a 64-byte read
+// of the control block after each batch of enqueued sweeps.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>

@@ -417,3 +417,22 @@ def test_welfare_gradient_is_derivative_of_optimal_welfare():
         E[i, j] = eps
         fd = (wstar(X, Y + E) - wstar(X, Y - E)) / (2 * eps)
         assert abs(fd - GY[i, j]) < 1e-6 * max(1.0, abs(fd)), (i, j, fd, GY[i, j])
+
+
+def test_workload_generators_are_seeded_and_shaped():
+    """The seeded inputs both sides share: same seed -> same bytes; the
+    configurations' shapes, dtypes and margin distributions."""
+    a = workloads.config_market(2, N=300, M=200)
+    b = workloads.config_market(2, N=300, M=200)
+    for x, y in zip((a.U, a.Q, a.V, a.P, a.n, a.m), (b.U, b.Q, b.V, b.P, b.n, b.m)):
+        assert np.array_equal(x, y)
+    assert a.U.dtype == np.float32 and a.U.shape == (300, 32) and a.V.shape == (200, 32)
+    assert np.all(a.n == 1.0) and set(np.unique(a.m)) <= {1.0, 2.0, 3.0, 4.0, 5.0}
+    c5 = workloads.config_market(5, N=1000, M=5000)
+    assert c5.m.min() >= 1 and c5.m.max() <= 1000 and c5.U.shape == (1000, 128)
+    reqs = workloads.serving_requests(count=64)
+    assert len(reqs) == 64 and reqs[0].arrival_s == 0.0
+    assert all(1000 <= r.N <= 200_000 and 1000 <= r.M <= 200_000 for r in reqs)
+    assert all(r.sigma in (0.5, 1.0) and r.d == 32 for r in reqs)
+    assert all(reqs[i].arrival_s <= reqs[i + 1].arrival_s for i in range(63))
+    assert workloads.serving_requests(count=64)[5] == reqs[5]
