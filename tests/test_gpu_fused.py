@@ -241,3 +241,39 @@ def test_autotuner_choice_and_cache(torch, lib, tmp_path):
     # the split count only reorders FP64 partial sums
     assert rel_err(a1.cpu().numpy(), a0.cpu().numpy()) < 1e-10
     assert rel_err(b1.cpu().numpy(), b0.cpu().numpy()) < 1e-10
+
+
+@pytest.mark.parametrize("compute", ["bf16", "fp8"])
+def test_input_dtypes_give_the_same_operands(torch, lib, compute):
+    """Factors given as FP64, FP32 or BF16 reach the packing as the same FP32
+    values when they are BF16-exact, so every input type gives bitwise the
+    same solve (ld_x/ld_y row strides wider than d included)."""
+    banner(f"input dtypes {compute}")
+    mk = workloads.config_market(3, N=700, M=900)
+    U, Q, V, P = (quant.bf16_round(x) for x in (mk.U, mk.Q, mk.V, mk.P))
+    n, m = to_dev(torch, mk.n), to_dev(torch, mk.m)
+    outs = []
+    for dt in (torch.float64, torch.float32, torch.bfloat16):
+        fs = []
+        for x in (U, Q, V, P):
+            wide = np.zeros((x.shape[0], x.shape[1] + 8), dtype=np.float32)
+            wide[:, :x.shape[1]] = x
+            fs.append(to_dev(torch, wide, dt)[:, :x.shape[1]])
+        a, b, info = lib.solve_market(*fs, n, m, mk.sigma, max_sweeps=7, compute=compute)
+        outs.append((a, b, info.residuals))
+    for a, b, r in outs[1:]:
+        assert torch.equal(a, outs[0][0]) and torch.equal(b, outs[0][1]) and r == outs[0][2]
+
+
+def test_serve_warm_start_matches_solve(torch, lib):
+    """A warm start b0 is honoured by the serving path exactly as by the
+    one-call solve."""
+    banner("serve warm start")
+    mk = workloads.config_market(2, N=3000, M=2500)
+    t = market_tensors(torch, mk)
+    b0 = torch.full((mk.M,), 0.7, dtype=torch.float64, device="cuda")
+    a1, b1, i1 = lib.solve_market(*t, mk.sigma, tol=1e-7, max_sweeps=80, b0=b0)
+    with lib.Server() as srv:
+        r = srv.wait(srv.submit(*t, mk.sigma, tol=1e-7, max_sweeps=80, b0=b0))
+    assert r.status == i1.status and r.info.sweeps == i1.sweeps
+    assert torch.equal(r.a, a1) and torch.equal(r.b, b1)
