@@ -174,6 +174,13 @@ struct Op<true> {  // FP8 e4m3, v_mfma_scale_f32_32x32x64_f8f6f4
 #define IPFP_TY 128
 #endif
 
+// Upper bound on waves per SIMD the compiler schedules the reduction pass for.
+// BF16 rows of 2d >= 192 fit three waves per SIMD when scheduled for it, but
+// an 8-wave workgroup uses only two of them, and the kernel compiled for two
+// (more registers per wave) is 15-60 % faster there (MI355X, N = M = 1e6);
+// elsewhere the default scheduling is as fast or faster.
+constexpr int pass_max_waves(int kp, bool fp8) { return (!fp8 && kp >= 192) ? 2 : 8; }
+
 constexpr int ty_for(int row_bytes) { return row_bytes <= 256 ? IPFP_TY : IPFP_TY / 2; }
 
 // Binary exponent e with w = m 2^e, m in [0.5, 1) (INT_MIN for w = 0).
@@ -521,7 +528,8 @@ __device__ __forceinline__ void fused_pass_body(
 }
 
 template <int KP, int XT, int WAVES, bool FP8, bool MAXMODE>
-__global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(WAVES * 64)
+    __attribute__((amdgpu_waves_per_eu(2, pass_max_waves(KP, FP8))))
     k_fused_pass(const uint8_t* __restrict__ Xo, const float* __restrict__ xscale,
                  const uint8_t* __restrict__ Yr, const float* __restrict__ yscale,
                  const double* __restrict__ wred, int red_dbuf, int exp_red,
@@ -548,7 +556,8 @@ __device__ __forceinline__ int group_find(const int32_t* __restrict__ first, int
 }
 
 template <int KP, int XT, int WAVES, bool FP8>
-__global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(WAVES * 64)
+    __attribute__((amdgpu_waves_per_eu(2, pass_max_waves(KP, FP8))))
     k_group_pass(const GroupHalf* __restrict__ g, const int32_t* __restrict__ idx,
                  const int32_t* __restrict__ first, int count) {
   const int j = group_find(first, count, (int)blockIdx.x);
