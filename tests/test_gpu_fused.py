@@ -277,3 +277,23 @@ def test_serve_warm_start_matches_solve(torch, lib):
         r = srv.wait(srv.submit(*t, mk.sigma, tol=1e-7, max_sweeps=80, b0=b0))
     assert r.status == i1.status and r.info.sweeps == i1.sweeps
     assert torch.equal(r.a, a1) and torch.equal(r.b, b1)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("cfg,N,M,sweeps", [(2, 20000, 20000, 12), (3, 20000, 20000, 12),
+                                            (5, 40000, 4001, 10)])
+def test_full_trajectory_at_20k(torch, lib, cfg, N, M, sweeps):
+    """Whole trajectories at tens of thousands of users per side in the
+    configurations' distributions (many workgroups, several splits, ragged
+    tails), against the FP64 oracle on the same quantised operands; the
+    residual history must match check by check."""
+    banner(f"full trajectory C{cfg} {N}x{M}")
+    mk = workloads.config_market(cfg, N=N, M=M)
+    t = market_tensors(torch, mk)
+    a, b, info = lib.solve_market(*t, mk.sigma, max_sweeps=sweeps, check_every=2)
+    K, r = oracle_quantised(mk, "bf16", sweeps, check_every=2)
+    del K
+    assert info.sweeps == r.sweeps == sweeps
+    assert rel_err(a.cpu().numpy(), r.a) < 2e-5
+    assert rel_err(b.cpu().numpy(), r.b) < 2e-5
+    np.testing.assert_allclose(info.residuals, r.res_hist, rtol=1e-4, atol=3e-7)
