@@ -251,7 +251,7 @@ def main():
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has "
               "no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
