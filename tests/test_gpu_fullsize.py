@@ -1,6 +1,13 @@
-"""Sampled parity at full size: the N = M = 10^6, d = 64 BF16 market in the
-launch configuration the benchmark times (automatic splits and tiles), and
-the unbalanced N = 2x10^6, M = 2x10^5, d = 128 FP8 market.
+"""Parity at full size: the N = M = 10^6, d = 64 BF16 market in the launch
+configuration the benchmark times (automatic splits and tiles), and the
+unbalanced N = 2x10^6, M = 2x10^5, d = 128 market in FP8 and BF16.
+
+Two checks per shape.
+* Separable surplus phi_xy = alpha_x + gamma_y, carried by factors padded to
+  the full d so the same kernel instantiation runs: K is rank one and the
+  oracle replays the exact Gauss-Seidel iterate sequence in O(N + M) per sweep
+  (eq. 6), so every row and column of every sweep is compared.
+* General factors: one half-sweep on sampled outputs, described below.
 
 The whole FP64 trajectory at these sizes is out of the oracle's reach, so one
 half-sweep is checked on sampled outputs with the GPU's own other-side
@@ -14,11 +21,14 @@ import pytest
 
 import workloads
 from helpers import banner, market_tensors, rel_err, require_gpu
-from oracle import ipfp as O, quant
+from oracle import closed, ipfp as O, quant
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 SAMPLE = 192
+# log2(e) / 2: the operand prescale sqrt(log2(e) / (2 sigma)) is exactly 1, so
+# surplus values that are exact in the operand type stay exact in the kernel
+SIGMA_UNIT = 0.7213475204444817
 
 
 @pytest.fixture(scope="module")
@@ -85,3 +95,43 @@ def test_c5_fp8_full_size_sampled(torch, lib):
     banner("C5 full size N=2e6 M=2e5 d=128 fp8, sampled half-steps")
     mk = workloads.config_market(5, sigma=1.0)
     check_half_steps(torch, lib, mk, "fp8", sweeps=2)
+
+
+@pytest.mark.parametrize("N,M,d,compute,margins,sweeps", [
+    (1_000_000, 1_000_000, 64, "bf16", "uint1-10", 8),
+    (2_000_000, 200_000, 128, "fp8", "zipf1.5cap1000", 6),
+    (2_000_000, 200_000, 128, "bf16", "zipf1.5cap1000", 6)])
+def test_full_size_separable_replay(torch, lib, N, M, d, compute, margins, sweeps):
+    banner(f"full-size separable replay {N}x{M} d={d} {compute}")
+    rng = np.random.default_rng(N + M + d)
+    # multiples of 1/8 in [-1, 1]: exact in BF16, and in e4m3 under the
+    # power-of-two scale of a row whose largest entry is 1
+    al = rng.integers(-8, 9, N) / 8.0
+    ga = rng.integers(-8, 9, M) / 8.0
+    U = np.zeros((N, d), np.float32)
+    V = np.zeros((M, d), np.float32)
+    U[:, 0], U[:, 1] = al, 1.0
+    V[:, 0], V[:, 1] = 1.0, ga
+    # the operands the kernel sees equal the factors exactly
+    for A in (U[:64], V[:64]):
+        full = np.concatenate([A, np.zeros_like(A)], 1)
+        got = quant.packed_rows(full, SIGMA_UNIT, compute)[:, :2 * d]
+        assert np.array_equal(got, full)
+    n = np.ones(N)
+    m = workloads._col_margins(rng, M, margins)
+    r = closed.separable_replay(al, ga, n, m, SIGMA_UNIT, max_sweeps=sweeps, check_every=1)
+    t = [torch.from_numpy(A).cuda() for A in (U, V)]
+    del U, V
+    Z = [torch.zeros_like(x) for x in t]
+    a, b, info = lib.solve_market(t[0], Z[0], t[1], Z[1], torch.from_numpy(n).cuda(),
+                                  torch.from_numpy(m).cuda(), SIGMA_UNIT, tol=0.0,
+                                  max_sweeps=sweeps, check_every=1, compute=compute)
+    ea = rel_err(a.cpu().numpy(), r.a)
+    eb = rel_err(b.cpu().numpy(), r.b)
+    print(f"separable replay {compute} {N}x{M}: rel err a {ea:.2e}, b {eb:.2e}, "
+          f"residuals {info.residuals[-1]:.3e} vs {r.res_hist[-1]:.3e}", flush=True)
+    del t, Z
+    torch.cuda.empty_cache()
+    assert info.sweeps == sweeps
+    assert ea < 2e-5 and eb < 2e-5
+    np.testing.assert_allclose(info.residuals, r.res_hist, rtol=1e-4, atol=3e-7)
