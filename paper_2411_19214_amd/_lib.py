@@ -152,6 +152,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         raise ImportError(
             f"{path} is missing: build it with `python -m paper_2411_19214_amd.build`"
             " (the IPFP kernels exist only as HIP code)")
+    # The library must share the HIP runtime torch uses (device pointers and
+    # streams cross the boundary). torch ships its own libamdhip64 under the
+    # same soname; loading torch first makes the dynamic linker reuse it, where
+    # loading this library first would map a second runtime from /opt/rocm.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

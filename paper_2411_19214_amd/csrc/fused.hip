@@ -241,13 +241,14 @@ __device__ __forceinline__ floatx16 mfma_step(const Frag& a, const Frag& b, floa
 // The reduction pass. MAXMODE: per (split, row) maximum of T over the split
 // (set-up). Otherwise the weighted sum S described at the top of this file.
 //
-// Where the MFMAs dominate a step (FP8 operands, BF16 with 2d = 128) sum mode
-// runs two independent accumulators ("chains") at a time -- the two output
-// tiles of a wave (XT = 2) or two consecutive reduced subtiles (XT = 1) -- so
-// consecutive MFMAs never wait on each other, and the exp2/FMA epilogue of the
-// previous pair is spread between this pair's MFMAs: the matrix cores and the
-// transcendental/FMA pipe then work at the same time. Elsewhere it finishes
-// one accumulator (MFMAs, then its epilogue) before the next.
+// Where the MFMAs dominate a step (FP8 operands, BF16 with 2d = 128 or
+// 2d >= 192) sum mode runs two independent accumulators ("chains") at a time
+// -- the two output tiles of a wave (XT = 2) or two consecutive reduced
+// subtiles (XT = 1) -- so consecutive MFMAs never wait on each other, and the
+// exp2/FMA epilogue of the previous pair is spread between this pair's MFMAs:
+// the matrix cores and the transcendental/FMA pipe then work at the same time.
+// Elsewhere it finishes one accumulator (MFMAs, then its epilogue) before the
+// next.
 //
 // `bid` is the workgroup's index within this market's grid (blockIdx.x for a
 // single-market launch, the offset within the market's range of a grouped
@@ -367,8 +368,12 @@ __device__ __forceinline__ void fused_pass_body(
   // and their running-sum slots; a zero-weight dummy before the first tile
   constexpr int NPAIR = XT == 2 ? SUB : SUB / 2;
   // the paired, pipelined schedule pays off where the MFMAs dominate a step
-  // (FP8 operands, BF16 with 2d = 128); elsewhere one chain at a time
-  constexpr bool kPaired = FP8 || KP == 128;
+  // (FP8 operands, BF16 with 2d = 128 or 2d >= 192); elsewhere one chain at
+  // a time
+  constexpr bool kPaired = FP8 || KP == 128 || KP >= 192;
+  // BF16 with 2d = 128: explicit scheduling groups (below) interleave each
+  // MFMA with its share of the pending epilogue
+  constexpr bool kGrouped = !FP8 && KP == 128;
   floatx16 pc0, pc1;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -412,6 +417,8 @@ __device__ __forceinline__ void fused_pass_body(
     const int buf = (tile - t0) & 1;
     const int wnext = wbuf == 2 ? 0 : wbuf + 1;
     gload(min(tile + 1, t1 - 1));   // prefetch (the last iteration reloads harmlessly)
+    // the next stage's global loads go out before any of this stage's work
+    if constexpr (!MAXMODE && kGrouped) __builtin_amdgcn_sched_barrier(0);
     if constexpr (MAXMODE) {
 #pragma unroll
       for (int sub = 0; sub < SUB; ++sub) {
@@ -493,6 +500,26 @@ __device__ __forceinline__ void fused_pass_body(
             if (s * PER + u < 16) epi1(s * PER + u, w0, w1, s4);
         }
         flush(s4);
+        if constexpr (kGrouped) {
+          // scheduling groups (masks: 0x008 MFMA, 0x400 transcendental,
+          // 0x002 other VALU, 0x100 LDS read): the weight reads and two
+          // k-steps of fragment reads first, then each MFMA followed by its
+          // share of the pending epilogue (PER exp2, PER FMAs) and the next
+          // fragment read. Without them the compiler clusters the epilogue
+          // after the first MFMAs and leaves the rest back to back.
+          __builtin_amdgcn_sched_group_barrier(0x100, 4 + 2, 0);
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x400, PER, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, PER, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x400, PER, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, PER, 0);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
         pc0 = a0;
         pc1 = a1;
         pw0 = &ws[wbuf][sub0 * 32 + 4 * h];

@@ -153,3 +153,22 @@ def test_tune_cache_keys_and_roundtrip(tmp_path):
     assert tune._load(path) == {}
     tune._store(path, {k1: {"options": {"tile_rows": 512, "splits": 0}}})
     assert tune._load(path)[k1]["options"] == {"tile_rows": 512, "splits": 0}
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading the library before anything imports torch still leaves a single
+    HIP runtime mapped (the one torch ships), so torch's device pointers and
+    streams are valid on both sides of the boundary."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2411_19214_amd import _lib\n"
+            "_lib.load()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().split('\\n')\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n"
+            % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"
