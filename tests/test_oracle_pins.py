@@ -436,3 +436,25 @@ def test_workload_generators_are_seeded_and_shaped():
     assert all(r.sigma in (0.5, 1.0) and r.d == 32 for r in reqs)
     assert all(reqs[i].arrival_s <= reqs[i + 1].arrival_s for i in range(63))
     assert workloads.serving_requests(count=64)[5] == reqs[5]
+
+
+def test_jacobi_sweeps_interleave_two_gauss_seidel_chains():
+    """The symmetric single-pass variant (both half-steps from the previous
+    sweep's scalings, one kernel evaluation per sweep) is two independent
+    copies of the eq. 6 iteration run on alternate sweeps: its u after sweep
+    2k - 1 and its v after sweep 2k are exactly the Gauss-Seidel iterate of
+    sweep k. So it spends as many kernel evaluations as the paper's order for
+    the same iterate, and cannot converge in fewer of them."""
+    Phi, n, m, beta = small_market(40, 30, seed=5)
+    K = ipfp.kernel_matrix(Phi, beta)
+    sweeps = 6
+    gs = [ipfp.ipfp_batch(K, n, m, max_sweeps=k) for k in range(1, sweeps + 1)]
+    u, v = np.ones(40), np.ones(30)
+    ju, jv = [], []
+    for _ in range(2 * sweeps):
+        u, v = ipfp.root(n, 0.5 * (K @ v)), ipfp.root(m, 0.5 * (K.T @ u))
+        ju.append(u)
+        jv.append(v)
+    for k in range(1, sweeps + 1):
+        np.testing.assert_array_equal(ju[2 * k - 2], gs[k - 1].a)
+        np.testing.assert_array_equal(jv[2 * k - 1], gs[k - 1].b)
