@@ -458,3 +458,34 @@ def test_jacobi_sweeps_interleave_two_gauss_seidel_chains():
     for k in range(1, sweeps + 1):
         np.testing.assert_array_equal(ju[2 * k - 2], gs[k - 1].a)
         np.testing.assert_array_equal(jv[2 * k - 1], gs[k - 1].b)
+
+
+def test_golden_equilibria_computed_in_mpmath():
+    """Small markets solved to 60 digits by Newton's method on eq. 5 in mpmath
+    (``tests/golden/equilibria.json``, written by
+    ``tests/golden/make_golden.py``, which uses no oracle code): the oracle's
+    converged IPFP reproduces a, b and mu (eq. 4), and the IPFP-free primal
+    Newton solve reproduces mu and the welfare of eq. 2."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "equilibria.json")
+    with open(path) as f:
+        data = json.load(f)
+    assert len(data["markets"]) >= 4
+    for mk in data["markets"]:
+        Phi = np.array(mk["phi"], dtype=np.float64)
+        n = np.array(mk["n"], dtype=np.float64)
+        m = np.array(mk["m"], dtype=np.float64)
+        beta = float(mk["beta"])
+        a = np.array(mk["a"], dtype=np.float64)
+        b = np.array(mk["b"], dtype=np.float64)
+        mu = np.array(mk["mu"], dtype=np.float64)
+        K = ipfp.kernel_matrix(Phi, beta)
+        r = ipfp.ipfp_batch(K, n, m, tol=1e-15, max_sweeps=200000)
+        np.testing.assert_allclose(r.a, a, rtol=1e-12, err_msg=mk["name"])
+        np.testing.assert_allclose(r.b, b, rtol=1e-12, err_msg=mk["name"])
+        np.testing.assert_allclose(ipfp.matching(K, r.a, r.b), mu, rtol=1e-12,
+                                   err_msg=mk["name"])
+        br = brute.primal_newton(Phi, n, m, beta)
+        np.testing.assert_allclose(br.mu, mu, rtol=1e-9, err_msg=mk["name"])
+        assert abs(br.value - float(mk["welfare"])) <= 1e-10 * abs(float(mk["welfare"]))
