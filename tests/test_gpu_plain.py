@@ -140,3 +140,25 @@ def test_not_converged_status(torch, lib):
     a, b, info = lib.solve_market(U, Q, V, P, n, m, mk.sigma, tol=1e-14, max_sweeps=3,
                                   path="plain", compute="f64")
     assert info.status == 1 and info.sweeps == 3 and len(info.residuals) == 3
+
+
+def test_golden_equilibria_fp64(torch, lib):
+    """The plain FP64 path on the markets solved to 60 digits in mpmath
+    (eq. 5; ``tests/golden/equilibria.json``): a, b within 1e-12 relative."""
+    import json
+    import os
+    banner("golden equilibria plain f64")
+    path = os.path.join(os.path.dirname(__file__), "golden", "equilibria.json")
+    with open(path) as f:
+        markets = json.load(f)["markets"]
+    for mk in markets:
+        Phi = np.array(mk["phi"], dtype=np.float64)
+        n = np.array(mk["n"], dtype=np.float64)
+        m = np.array(mk["m"], dtype=np.float64)
+        a, b, info = lib.solve_market_phi(to_dev(torch, Phi), to_dev(torch, n),
+                                          to_dev(torch, m), float(mk["beta"]), tol=1e-15,
+                                          max_sweeps=4000, check_every=10, compute="f64")
+        print(f"golden {mk['name']}: {info.sweeps} sweeps, residual {info.final_res:.1e}",
+              flush=True)
+        assert rel_err(a.cpu().numpy(), np.array(mk["a"], dtype=np.float64)) < 1e-12
+        assert rel_err(b.cpu().numpy(), np.array(mk["b"], dtype=np.float64)) < 1e-12
