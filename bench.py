@@ -10,11 +10,14 @@ Default workload: the fused BF16 path on the N = M = 1,000,000, d = 64
 market (factors N(0, 1/64), sigma = 1, n = 1, m uniform on 1..10), with the
 factors resident in HBM before timing starts. The same JSON line also reports
 the plain FP32 (materialised K) and fused BF16 paths on the 20,000 x 20,000,
-d = 32 market at a fixed 500 sweeps, the serving mix (512 markets arriving
-at 200/s, p50/p99 solve latency), the roofline of the dominant kernel and the
-CPU oracle timed on a bounded sample of the default workload.
+d = 32 market at a fixed 500 sweeps, the solve's outputs on the default
+market (top-k lists, welfare gradient, stable factors), the serving mix (512
+markets arriving at 200/s, p50/p99 solve latency), the roofline of the
+dominant kernel and the CPU oracle timed on a bounded sample of the default
+workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c2] [--no-serve]
+                    [--no-outputs]
 """
 from __future__ import annotations
 
@@ -75,7 +78,7 @@ def measured_traffic(n_rows):
     return rec["traffic_bytes_per_launch"]
 
 
-def run_fused(torch, L, mk, steps, warmup, compute="bf16"):
+def run_fused(torch, L, mk, steps, warmup, compute="bf16", outputs=False):
     """Resident market: warm up, then time exactly `steps` sweeps."""
     U, Q, V, P, n, m = factor_tensors(torch, mk)
     h = L.Market(U, Q, V, P, n, m, mk.sigma, tol=0.0, max_sweeps=warmup + steps + 1,
@@ -94,11 +97,47 @@ def run_fused(torch, L, mk, steps, warmup, compute="bf16"):
     _, _, after = h.read()
     h.run(1)                       # final residual of the last state (untimed)
     _, _, fin = h.read()
+    outs = run_outputs(torch, L, h, mk, (U, Q, V, P)) if outputs else None
     h.close()
     launches = after.pass_launches - before.pass_launches
     pass_ms = after.pass_ms - before.pass_ms
     return dict(ms=ms, pass_ms=pass_ms, launches=launches, final_res=fin.final_res,
-                setup_ms=before.setup_ms, fixups=fin.fixups, sweeps=fin.sweeps)
+                setup_ms=before.setup_ms, fixups=fin.fixups, sweeps=fin.sweeps, outputs=outs)
+
+
+def run_outputs(torch, L, h, mk, factors, reps=3, k=10):
+    """The solve's outputs at the market's final state, each call timed on the
+    host around a synchronous library call (scratch allocation included):
+    top-k lists for every candidate (one fused pass with a top-k epilogue,
+    4d flops per pair), the welfare gradient for the candidates' factors (one
+    fused pass of three products, 12d flops per pair) and the stable factors
+    of eq. 11 (O((N + M) d))."""
+    N, M, d = mk.N, mk.M, mk.d
+
+    def timed(fn):
+        fn()                                   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, out
+
+    res = {}
+    dt, _ = timed(lambda: h.topk(k, 0))
+    tf = 4.0 * d * N * M / dt / 1e12
+    res["topk"] = {"k": k, "rows": N, "call_ms": dt * 1e3, "pair_evals_per_s": N * M / dt,
+                   "tflops": tf, "frac_of_bf16_peak": tf / PEAK_BF16_TFLOPS}
+    dt, _ = timed(lambda: h.gradient(0))
+    tf = 12.0 * d * N * M / dt / 1e12
+    res["gradient"] = {"rows": N, "width": 2 * d, "call_ms": dt * 1e3,
+                       "pair_evals_per_s": N * M / dt, "tflops": tf,
+                       "frac_of_bf16_peak": tf / PEAK_BF16_TFLOPS}
+    a, b, _ = h.read()
+    U, Q, V, P = factors
+    dt, _ = timed(lambda: L.stable_factors(U, Q, V, P, mk.sigma, a, b))
+    res["stable_factors"] = {"rows": N + M, "width": 2 * d + 2, "call_ms": dt * 1e3}
+    return res
 
 
 def run_c2(torch, L, sweeps=500):
@@ -239,6 +278,8 @@ def main():
     ap.add_argument("--size", type=int, default=1_000_000,
                     help="N = M of the default workload (1e6 unless testing)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-outputs", action="store_true",
+                    help="skip timing top-k, gradient and stable factors")
     ap.add_argument("--aging-ms", type=float, default=0.0,
                     help="serving: waiting time worth a halving of N*M (0 = library default)")
     ap.add_argument("--lane-blocks", type=int, default=0,
@@ -277,7 +318,7 @@ def main():
     log(f"generating C3 market N=M={args.size} d={cfg['d']}")
     mk = workloads.config_market(3, N=args.size, M=args.size)
     log("timing fused BF16")
-    r = run_fused(torch, L, mk, args.steps, args.warmup)
+    r = run_fused(torch, L, mk, args.steps, args.warmup, outputs=not args.no_outputs)
     N, M, d = mk.N, mk.M, mk.d
     value = 2.0 * N * M * args.steps / (r["ms"] / 1e3)
     avg_launch_s = r["pass_ms"] / r["launches"] / 1e3
@@ -313,6 +354,8 @@ def main():
                      "flops_per_launch": flops_per_launch,
                      "exp2_per_s": exp_rate},
     }
+    if r["outputs"] is not None:
+        line["outputs"] = r["outputs"]
     if not args.no_c2:
         log("C2: plain FP32 vs fused BF16, 500 sweeps")
         line["c2_20k"] = run_c2(torch, L)
