@@ -42,6 +42,8 @@
 namespace ipfp {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
 typedef int intx4 __attribute__((ext_vector_type(4)));
@@ -974,18 +976,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
       for (int ks = 0; ks < 2; ++ks) {
         // B operand: this lane's P at K slots 8h..8h+7 (reduced rows
         // 16 ks + 8 (i / 4) + 4 h + i % 4), high and low BF16 parts
-        uint16_t hi[8], lo[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const float v = p[8 * ks + i];
-          hi[i] = bf16_rne(v);
-          lo[i] = bf16_rne(v - __uint_as_float((uint32_t)hi[i] << 16));
-        }
+        // (hardware round-to-nearest-even conversions, two values each;
+        // v - hi is exact in FP32)
         bf16x8 bh, bl;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          reinterpret_cast<uint16_t*>(&bh)[i] = hi[i];
-          reinterpret_cast<uint16_t*>(&bl)[i] = lo[i];
+        for (int i = 0; i < 8; i += 2) {
+          const floatx2 v = {p[8 * ks + i], p[8 * ks + i + 1]};
+          const bf16x2 hv = __builtin_convertvector(v, bf16x2);
+          const floatx2 rest = v - __builtin_convertvector(hv, floatx2);
+          const bf16x2 lv = __builtin_convertvector(rest, bf16x2);
+          bh[i] = hv[0];
+          bh[i + 1] = hv[1];
+          bl[i] = lv[0];
+          bl[i + 1] = lv[1];
         }
         const int r0 = sub * 32 + 16 * ks + 4 * h;   // rows r0..r0+3, r0+8..r0+11
 #pragma unroll
