@@ -170,7 +170,7 @@ int ipfp_solve_market(ipfp_ctx *ctx, const ipfp_market *mk,
 int ipfp_tune(ipfp_ctx *ctx, const ipfp_market *mk, const ipfp_options *opt,
               ipfp_options *best, double *best_ms, void *stream);
 
-/* Solve a market given by a dense surplus Phi/* Solve a market given by a dense surplus Phi (N x M device matrix, dtype
+/* Solve a market given by a dense surplus Phi (N x M device matrix, dtype
  * F32 or F64, row stride ld_phi): batch IPFP of eq. 7 / Alg. 1 on the plain
  * path. opt->path is ignored; opt->compute chooses F32 or F64 storage of K. */
 int ipfp_solve_market_phi(ipfp_ctx *ctx, int64_t N, int64_t M,
@@ -247,26 +247,14 @@ int ipfp_market_topk(ipfp_handle *h, int side, int32_t k, int32_t *idx_out,
  * mu = 2^T a b with T from the packed rows, and the packed rows divided by
  * their prescale as the factor values (the factors as the matrix cores see
  * them). g_out: rows x 2d FP64 device, row stride ld_g >= 2d. Scratch of
- * splits x rows x kpad doubles is allocated for the call and charged to the
- * context budget. IPFP_EINVAL for the plain path or FP8 operands. */
+ * splits x rows x kpad doubles plus a column-major copy of the other side's
+ * packed rows (kpad x its row count, rounded up to the stage height, 2 bytes
+ * each) is allocated for the call and charged to the context budget.
+ * IPFP_EINVAL for the plain path or FP8 operands. */
 int ipfp_market_gradient(ipfp_handle *h, int side, double *g_out, int64_t ld_g,
                          void *stream);
 
-/* The fused path's packed operand of one side/* The fused path's packed operand of one side/* Gradient of the optimal welfare with respect to the factors (Sec. 5 names
- * back-propagation into the recommender as future work). At the optimum of
- * eq. 2-3, dW/dPhi_xy = mu_xy (envelope theorem), and Phi = [U|Q][V|P]^T
- * (eq. 8), so side 0 gives G = mu [V|P] = [dW/dU | dW/dQ] (N x 2d) and side
- * 1 gives G = mu^T [U|Q] = [dW/dV | dW/dP] (M x 2d). Computed for a resident
- * fused BF16 market at its current state, from the operands the solve uses:
- * mu = 2^T a b with T from the packed rows, and the packed rows divided by
- * their prescale as the factor values (the factors as the matrix cores see
- * them). g_out: rows x 2d FP64 device, row stride ld_g >= 2d. Scratch of
- * splits x rows x kpad doubles is allocated for the call and charged to the
- * context budget. IPFP_EINVAL for the plain path or FP8 operands. */
-int ipfp_market_gradient(ipfp_handle *h, int side, double *g_out, int64_t ld_g,
-                         void *stream);
-
-/* The fused path's packed operand of one side/* The fused path's packed operand of one side (Sec. 3.3's factor matrices as
+/* The fused path's packed operand of one side (Sec. 3.3's factor matrices as
  * the matrix cores read them): rows p [A|B] concatenated, zero-padded to
  * `kpad` columns and rounded to `compute`, where p = sqrt(log2(e)/(2 sigma))
  * rounded to FP32 (p = 1 when sigma = 0), applied in FP32 after rounding the

@@ -150,11 +150,13 @@ hipError_t launch_topk(const FusedPass& fp, const double* a_out, int k, int spli
                        float* pscore, int32_t* pidx, int32_t* idx_out, float* score_out,
                        hipStream_t s);
 // Welfare gradient of the output side, G = mu Y (N x width FP64, width = 2d):
-// BF16 operands only. Scratch: splits x rows x kpad doubles (gpart); *Eptr is
-// the largest binary exponent of fp.w_red.
+// BF16 operands only. Scratch: splits x rows x kpad doubles (gpart) and
+// gradient_scratch_bytes(kpad, reduced rows) bytes (yt, the column-major copy
+// of the reduced side); *Eptr is the largest binary exponent of fp.w_red.
+size_t gradient_scratch_bytes(int kpad, int64_t L);
 hipError_t launch_gradient(const FusedPass& fp, const int* Eptr, const double* a_out,
-                           double inv_p, int splits, double* gpart, int width, double* g,
-                           int64_t ld_g, hipStream_t s);
+                           double inv_p, int splits, double* gpart, uint16_t* yt, int width,
+                           double* g, int64_t ld_g, hipStream_t s);
 hipError_t launch_stable_factors(const void* A, const void* B, ipfp_dtype dt, int64_t ld,
                                  int64_t rows, int64_t d, double sigma, const double* w,
                                  int log_col, double* out, int64_t ld_out, hipStream_t s);

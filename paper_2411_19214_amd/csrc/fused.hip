@@ -853,38 +853,79 @@ hipError_t launch_topk(const FusedPass& fp, const double* a_out, int k, int spli
 // (the reduction pass's terms) and Ypk = p Y the packed value rows. The pass
 // is the reduction pass followed by a second product on the matrix cores
 // (flash-attention-forward shape): the 32 x 32 tile of P, split into BF16
-// high and low parts (about 16 significant bits together), times the staged
-// value tile. The value tile is staged a second time in LDS transposed
-// (columns contiguous, rows padded by 8 bytes against bank conflicts), so a
-// lane reads its eight K values as two 8-byte loads. The product's K order is
-// a permutation of the 32 reduced rows of a subtile that lets every lane feed
-// its own P values as the B operand. FP32 accumulators are folded into FP64
-// after every stage, in registers for packed rows up to 128 columns and in
-// the lane's own slots of the partial buffer (every fourth stage) above that;
-// one FP64 partial per (split, row, column) results.
+// high and low parts (about 16 significant bits together), times the value
+// tile. The product needs the value rows column-contiguous, so the packed
+// reduced side is first transposed once into a column-major copy (zero past
+// the last row); each stage then copies a block of it into LDS (columns
+// padded by 8 bytes against bank conflicts), and a lane reads its eight K
+// values as two 8-byte loads. The product's K order is a permutation of the
+// 32 reduced rows of a subtile that lets every lane feed its own P values as
+// the B operand. A workgroup (4 waves, one per SIMD: the FP64 sums take the
+// registers of a second) covers 128 output rows and up to four 32-column
+// blocks of G; wider rows take two column groups, each recomputing T. FP32
+// accumulators are folded into FP64 registers after every stage; one FP64
+// partial per (split, row, column) results.
+
+// Column-major copy of the packed reduced side: Yt[c][y] = Yr[y][c] for
+// y < L, 0 for L <= y < Lp. Grid (Lp / 64, KP / 32), 256 threads.
 template <int KP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ void __launch_bounds__(256)
+    k_transpose_packed(const uint8_t* __restrict__ Yr, int L, int Lp,
+                       uint16_t* __restrict__ Yt) {
+  constexpr int RB = KP * 2;
+  __shared__ __attribute__((aligned(16))) uint16_t tile[32][72];   // [column][row]
+  const int t = threadIdx.x;
+  const int y0 = blockIdx.x * 64, c0 = blockIdx.y * 32;
+  {
+    const int r = t >> 2, j = t & 3;          // 64 rows x 4 chunks of 8 columns
+    const int y = y0 + r;
+    intx4 v = intx4{0, 0, 0, 0};
+    if (y < L) v = *reinterpret_cast<const intx4*>(Yr + (int64_t)y * RB + (c0 + 8 * j) * 2);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      tile[8 * j + i][r] = (uint16_t)((uint32_t)v[i >> 1] >> (16 * (i & 1)));
+  }
+  __syncthreads();
+  {
+    const int c = t >> 3, q = t & 7;          // 32 columns x 8 chunks of 8 rows
+    *reinterpret_cast<intx4*>(Yt + (int64_t)(c0 + c) * Lp + y0 + 8 * q) =
+        *reinterpret_cast<const intx4*>(&tile[c][8 * q]);
+  }
+}
+
+// 32-column blocks of G per workgroup, and waves per workgroup
+constexpr int grad_col_blocks(int kp) { return kp / 32 < 4 ? kp / 32 : 4; }
+constexpr int kGradWaves = 4;
+
+template <int KP>
+__global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
     k_grad_pass(const uint8_t* __restrict__ Xo, const uint8_t* __restrict__ Yr,
-                const double* __restrict__ wred, const int* __restrict__ Eptr,
-                const float* __restrict__ shift, int R, int L, int tiles_per_split,
-                int nsplit, double* __restrict__ gpart) {
-  constexpr int WAVES = 4;
+                const uint16_t* __restrict__ Yt, int Lp, const double* __restrict__ wred,
+                const int* __restrict__ Eptr, const float* __restrict__ shift, int R, int L,
+                int tiles_per_split, int nsplit, int ngroups, double* __restrict__ gpart) {
+  constexpr int WAVES = kGradWaves;
   typedef PassCore<KP, 1, WAVES, false> C;
   typedef typename C::Frag Frag;
   typedef Op<false> O;
   constexpr int RB = C::RB, kTY = C::kTY, NS = C::NS, LS = C::LS, NT = C::NT;
   constexpr int CH = C::CH, CPT = C::CPT, SUB = C::SUB;
-  constexpr int NB = KP / 32;              // 32-column blocks of the value rows
-  constexpr int TS = kTY * 2 + 8;          // bytes per transposed (column) row
+  constexpr int NB = KP / 32;               // 32-column blocks of the value rows
+  constexpr int NBL = grad_col_blocks(KP);  // ... handled by one workgroup
+  constexpr int TS = kTY * 2 + 8;           // bytes per staged column
+  constexpr int CCH = kTY * 2 / 16;         // 16-byte chunks per staged column
+  constexpr int CHT = NBL * 32 * CCH;
+  constexpr int CPTT = (CHT + NT - 1) / NT;
   __shared__ __attribute__((aligned(16))) uint8_t ys[2][kTY * LS];
-  __shared__ __attribute__((aligned(16))) uint8_t yt[2][KP * TS];
+  __shared__ __attribute__((aligned(16))) uint8_t yt[2][NBL * 32 * TS];
   __shared__ __attribute__((aligned(16))) float ws[2][kTY];
 
   int E = *Eptr;
   if (E == INT_MIN) E = 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
-  const int split = blockIdx.x % nsplit, rb = blockIdx.x / nsplit;
+  const int grp = blockIdx.x % ngroups, rest = blockIdx.x / ngroups;
+  const int split = rest % nsplit, rb = rest / nsplit;
+  const int nb0 = grp * NBL, nbn = min(NBL, NB - nb0);
   const int T = (L + kTY - 1) / kTY;
   const int t0 = split * tiles_per_split, t1 = min(T, t0 + tiles_per_split);
   const int x = (rb * WAVES + wave) * 32 + l32;
@@ -901,25 +942,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
     }
   }
   const float hv = ok ? shift[x] : 0.f;
-  constexpr bool kRegs = KP <= 128;        // FP64 sums in registers
-  constexpr int kG = kRegs ? 1 : 16;       // FP64 slots when kept in memory
-  floatx16 g32[NB];
-  double g64[kRegs ? NB : 1][kRegs ? 16 : 1];
+  floatx16 g32[NBL];
+  double g64[NBL][16];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
+  for (int nb = 0; nb < NBL; ++nb)
 #pragma unroll
-    for (int j = 0; j < 16; ++j) g32[nb][j] = 0.f;
-  if constexpr (kRegs) {
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) g64[nb][j] = 0.0;
-  }
-  (void)kG;
-  double* dst = gpart + ((int64_t)split * R + (ok ? x : 0)) * KP;
-  bool first = true;
+    for (int j = 0; j < 16; ++j) {
+      g32[nb][j] = 0.f;
+      g64[nb][j] = 0.0;
+    }
 
-  intx4 pre[CPT];
+  intx4 pre[CPT], pret[CPTT];
   float pw = 0.f;
   auto gload = [&](int tile) {
 #pragma unroll
@@ -928,6 +961,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
       const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
       const uint32_t y = (uint32_t)min(tile * kTY + r, L - 1);
       pre[q] = *reinterpret_cast<const intx4*>(Yr + cb * 16 + (uint64_t)y * RB);
+    }
+#pragma unroll
+    for (int q = 0; q < CPTT; ++q) {
+      const int chunk = min(tid + q * NT, CHT - 1);
+      const int cl = chunk / CCH, j = chunk % CCH;
+      const int c = min(32 * nb0 + cl, KP - 1);   // a short last group repeats a column
+      pret[q] = *reinterpret_cast<const intx4*>(
+          Yt + (int64_t)c * Lp + (int64_t)tile * kTY + 8 * j);
     }
     const int y = tile * kTY + (tid % kTY);
     pw = y < L ? (float)ldexp(wred[min(y, L - 1)], -E) : 0.f;
@@ -938,13 +979,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
       const int chunk = min(tid + q * NT, CH - 1);
       const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
       *reinterpret_cast<intx4*>(&ys[buf][r * LS + cb * 16]) = pre[q];
-      // transposed copy: element c = 8 cb + i of row r to yt[c][r]
+    }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const uint32_t word = (uint32_t)pre[q][i >> 1];
-        *reinterpret_cast<uint16_t*>(&yt[buf][(cb * 8 + i) * TS + r * 2]) =
-            (uint16_t)(word >> (16 * (i & 1)));
-      }
+    for (int q = 0; q < CPTT; ++q) {
+      const int chunk = min(tid + q * NT, CHT - 1);
+      const int cl = chunk / CCH, j = chunk % CCH;
+      uint8_t* d = &yt[buf][cl * TS + 16 * j];
+      *reinterpret_cast<int2*>(d) = int2{pret[q][0], pret[q][1]};
+      *reinterpret_cast<int2*>(d + 8) = int2{pret[q][2], pret[q][3]};
     }
     ws[buf][tid % kTY] = pw;
   };
@@ -982,72 +1024,53 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
 #pragma unroll
         for (int i = 0; i < 8; i += 2) {
           const floatx2 v = {p[8 * ks + i], p[8 * ks + i + 1]};
-          const bf16x2 hv = __builtin_convertvector(v, bf16x2);
-          const floatx2 rest = v - __builtin_convertvector(hv, floatx2);
-          const bf16x2 lv = __builtin_convertvector(rest, bf16x2);
-          bh[i] = hv[0];
-          bh[i + 1] = hv[1];
+          const bf16x2 hv2 = __builtin_convertvector(v, bf16x2);
+          const floatx2 rest2 = v - __builtin_convertvector(hv2, floatx2);
+          const bf16x2 lv = __builtin_convertvector(rest2, bf16x2);
+          bh[i] = hv2[0];
+          bh[i + 1] = hv2[1];
           bl[i] = lv[0];
           bl[i + 1] = lv[1];
         }
         const int r0 = sub * 32 + 16 * ks + 4 * h;   // rows r0..r0+3, r0+8..r0+11
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          // A operand: value column 32 nb + l32 at the same eight rows
-          const uint8_t* col = &yt[buf][(32 * nb + l32) * TS];
-          intx4 av;
-          const int2 v0 = *reinterpret_cast<const int2*>(col + r0 * 2);
-          const int2 v1 = *reinterpret_cast<const int2*>(col + (r0 + 8) * 2);
-          av[0] = v0.x;
-          av[1] = v0.y;
-          av[2] = v1.x;
-          av[3] = v1.y;
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&av);
-          g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, g32[nb], 0, 0, 0);
-          g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, g32[nb], 0, 0, 0);
-        }
-      }
-    }
-    // lane (o, h) holds columns 32 nb + 8 (j / 4) + 4 h + j % 4 of row o
-    if constexpr (kRegs) {
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          g64[nb][j] += (double)g32[nb][j];
-          g32[nb][j] = 0.f;
-        }
-    } else if (((tile - t0) & 3) == 3 || tile == t1 - 1) {
-      if (ok) {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            double* slot = dst + 32 * nb + 8 * (j >> 2) + 4 * h + (j & 3);
-            *slot = (first ? 0.0 : *slot) + (double)g32[nb][j];
+        for (int nb = 0; nb < NBL; ++nb) {
+          if (nb < nbn) {
+            // A operand: value column 32 (nb0 + nb) + l32 at the same eight rows
+            const uint8_t* col = &yt[buf][(32 * nb + l32) * TS];
+            intx4 av;
+            const int2 v0 = *reinterpret_cast<const int2*>(col + r0 * 2);
+            const int2 v1 = *reinterpret_cast<const int2*>(col + (r0 + 8) * 2);
+            av[0] = v0.x;
+            av[1] = v0.y;
+            av[2] = v1.x;
+            av[3] = v1.y;
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&av);
+            g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, g32[nb], 0, 0, 0);
+            g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, g32[nb], 0, 0, 0);
           }
+        }
       }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) g32[nb][j] = 0.f;
-      first = false;
     }
+    // lane (o, h) holds columns 32 (nb0 + nb) + 8 (j / 4) + 4 h + j % 4 of row o
+#pragma unroll
+    for (int nb = 0; nb < NBL; ++nb)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        g64[nb][j] += (double)g32[nb][j];
+        g32[nb][j] = 0.f;
+      }
     lstore(buf ^ 1);
     __syncthreads();
   }
   if (ok) {
-    if constexpr (kRegs) {
+    double* dst = gpart + ((int64_t)split * R + x) * KP + 32 * nb0;
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
+    for (int nb = 0; nb < NBL; ++nb)
+      if (nb < nbn) {
 #pragma unroll
         for (int j = 0; j < 16; ++j) dst[32 * nb + 8 * (j >> 2) + 4 * h + (j & 3)] = g64[nb][j];
-    } else if (first) {   // a split with no tiles
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) dst[32 * nb + 8 * (j >> 2) + 4 * h + (j & 3)] = 0.0;
-    }
+      }
   }
 }
 
@@ -1068,17 +1091,32 @@ __global__ void __launch_bounds__(256)
 }
 
 template <int KP>
-static hipError_t grad_t(const FusedPass& fp, const int* Eptr, const double* a_out, double inv_p,
-                         int splits, double* gpart, int width, double* g, int64_t ld_g,
-                         hipStream_t s) {
+static size_t grad_t_scratch(int64_t L) {
   constexpr int kTY = ty_for(KP * 2);
-  const int64_t rblocks = (fp.out.rows + 127) / 128;
+  return (size_t)KP * (size_t)((L + kTY - 1) / kTY * kTY) * sizeof(uint16_t);
+}
+
+template <int KP>
+static hipError_t grad_t(const FusedPass& fp, const int* Eptr, const double* a_out, double inv_p,
+                         int splits, double* gpart, uint16_t* yt, int width, double* g,
+                         int64_t ld_g, hipStream_t s) {
+  constexpr int kTY = ty_for(KP * 2);
+  constexpr int NB = KP / 32, NBL = grad_col_blocks(KP);
+  const int ngroups = (NB + NBL - 1) / NBL;
+  const int64_t rblocks = (fp.out.rows + kGradWaves * 32 - 1) / (kGradWaves * 32);
   const int T = (int)((fp.red.rows + kTY - 1) / kTY);
+  const int Lp = T * kTY;
   const int tps = (T + splits - 1) / splits;
-  hipLaunchKernelGGL((k_grad_pass<KP>), dim3((unsigned)(rblocks * splits)), dim3(256), 0, s,
-                     (const uint8_t*)fp.out.ops, (const uint8_t*)fp.red.ops, fp.w_red, Eptr,
-                     fp.shift, (int)fp.out.rows, (int)fp.red.rows, tps, splits, gpart);
+  hipLaunchKernelGGL((k_transpose_packed<KP>), dim3((unsigned)(Lp / 64), (unsigned)(KP / 32)),
+                     dim3(256), 0, s, (const uint8_t*)fp.red.ops, (int)fp.red.rows, Lp, yt);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_grad_pass<KP>), dim3((unsigned)(rblocks * splits * ngroups)),
+                     dim3(kGradWaves * 64),
+                     0, s, (const uint8_t*)fp.out.ops, (const uint8_t*)fp.red.ops,
+                     (const uint16_t*)yt, Lp, fp.w_red, Eptr, fp.shift, (int)fp.out.rows,
+                     (int)fp.red.rows, tps, splits, ngroups, gpart);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = fp.out.rows * width;
   hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, gpart,
@@ -1087,22 +1125,31 @@ static hipError_t grad_t(const FusedPass& fp, const int* Eptr, const double* a_o
   return hipGetLastError();
 }
 
+#define IPFP_GRAD_KPADS(X) X(32) X(64) X(96) X(128) X(160) X(192) X(224) X(256)
+
+size_t gradient_scratch_bytes(int kpad, int64_t L) {
+  switch (kpad) {
+#define IPFP_GRAD_CASE(K) \
+    case K: return grad_t_scratch<K>(L);
+    IPFP_GRAD_KPADS(IPFP_GRAD_CASE)
+#undef IPFP_GRAD_CASE
+    default: return 0;
+  }
+}
+
 hipError_t launch_gradient(const FusedPass& fp, const int* Eptr, const double* a_out,
-                           double inv_p, int splits, double* gpart, int width, double* g,
-                           int64_t ld_g, hipStream_t s) {
+                           double inv_p, int splits, double* gpart, uint16_t* yt, int width,
+                           double* g, int64_t ld_g, hipStream_t s) {
   if (fp.compute != IPFP_BF16) return hipErrorInvalidValue;
   switch (fp.kpad) {
-    case 32: return grad_t<32>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
-    case 64: return grad_t<64>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
-    case 96: return grad_t<96>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
-    case 128: return grad_t<128>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
-    case 160: return grad_t<160>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
-    case 192: return grad_t<192>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
-    case 224: return grad_t<224>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
-    case 256: return grad_t<256>(fp, Eptr, a_out, inv_p, splits, gpart, width, g, ld_g, s);
+#define IPFP_GRAD_CASE(K) \
+    case K: return grad_t<K>(fp, Eptr, a_out, inv_p, splits, gpart, yt, width, g, ld_g, s);
+    IPFP_GRAD_KPADS(IPFP_GRAD_CASE)
+#undef IPFP_GRAD_CASE
     default: return hipErrorInvalidValue;
   }
 }
+#undef IPFP_GRAD_KPADS
 
 // ---- combine partial sums, update scalings -----------------------------------
 
