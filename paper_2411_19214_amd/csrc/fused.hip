@@ -704,24 +704,43 @@ __global__ void __launch_bounds__(256)
     lstore(0);
   }
   __syncthreads();
+  // one subtile's T (an MFMA chain over the packed row)
+  auto tsub = [&](int buf, int sub) {
+    const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
+    const int asc = FP8 ? ysc[buf][sub * 32 + l32] : 127;
+    floatx16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      acc = mfma_step<FP8>(lds_frag<FP8, Frag>(arow, s), bfrag[s], acc, asc, xsc);
+    return acc;
+  };
   for (int tile = t0; tile < t1; ++tile) {
     const int buf = (tile - t0) & 1;
     gload(min(tile + 1, t1 - 1));
+    // the next subtile's MFMA chain is issued before this one's scores are
+    // checked, and the common case (no score above any lane's k-th best)
+    // takes a single branch per subtile, so the chain runs under the checks
+    floatx16 nxt = tsub(buf, 0);
 #pragma unroll
     for (int sub = 0; sub < SUB; ++sub) {
-      const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
-      const int asc = FP8 ? ysc[buf][sub * 32 + l32] : 127;
-      floatx16 acc;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-        acc = mfma_step<FP8>(lds_frag<FP8, Frag>(arow, s), bfrag[s], acc, asc, xsc);
+      const floatx16 acc = nxt;
+      if (sub + 1 < SUB) nxt = tsub(buf, sub + 1);
+      float sc[16];
+      float top = -INFINITY;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int yr = sub * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        const float sc = acc[r] + lws[buf][yr];
-        if (sc > ts[KT - 1]) topk_insert<KT>(ts, ti, sc, tile * kTY + yr);
+        sc[r] = acc[r] + lws[buf][yr];
+        top = fmaxf(top, sc[r]);
+      }
+      if (top > ts[KT - 1]) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int yr = sub * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+          if (sc[r] > ts[KT - 1]) topk_insert<KT>(ts, ti, sc[r], tile * kTY + yr);
+        }
       }
     }
     lstore(buf ^ 1);
