@@ -1015,18 +1015,27 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
     lstore(0);
   }
   __syncthreads();
+  // one subtile's T + h (an MFMA chain over the packed row)
+  auto tsub = [&](int buf, int sub) {
+    const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
+    floatx16 acc;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = hv;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      acc = mfma_step<false>(lds_frag<false, Frag>(arow, s), bfrag[s], acc, 127, 127);
+    return acc;
+  };
   for (int tile = t0; tile < t1; ++tile) {
     const int buf = (tile - t0) & 1;
     gload(min(tile + 1, t1 - 1));
+    // the next subtile's T chain is issued ahead of this subtile's exp2 and
+    // products, which do not depend on it
+    floatx16 nxt = tsub(buf, 0);
 #pragma unroll
     for (int sub = 0; sub < SUB; ++sub) {
-      const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
-      floatx16 acc;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) acc[j] = hv;
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-        acc = mfma_step<false>(lds_frag<false, Frag>(arow, s), bfrag[s], acc, 127, 127);
+      const floatx16 acc = nxt;
+      if (sub + 1 < SUB) nxt = tsub(buf, sub + 1);
       float p[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
