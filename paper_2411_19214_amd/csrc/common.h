@@ -208,6 +208,8 @@ hipError_t launch_group_check(const GroupCheck* c, int count, hipStream_t s);
 // pass must reproduce for bitwise-identical results).
 void fused_pass_grid(const FusedPass& fp, int64_t* blocks, int* tiles_per_split);
 int fused_auto_splits(int64_t R, int64_t L, int rows_per_wg);
+// Split count of the sum pass for a market side (automatic splits).
+int fused_pass_splits(int64_t R, int64_t L, int64_t kpad, ipfp_dtype compute, int tile_rows);
 int fused_rows_per_wg(int64_t kpad, ipfp_dtype compute, int tile_rows);
 int fused_default_tile_rows(int64_t kpad, ipfp_dtype compute);
 int fused_fixup_blocks();

@@ -35,6 +35,7 @@
 #include <limits.h>
 #include <math.h>
 
+#include <atomic>
 #include <type_traits>
 
 #include "common.h"
@@ -1461,10 +1462,10 @@ hipError_t launch_fused_shift(const FusedPass& fp, Ctl* ctl, hipStream_t s) {
 }
 
 // Default workgroup height (tile_rows = 0). Measured on MI355X at N = M = 1e6:
-// two-tile kernels that fit three waves per SIMD (BF16 with 2d = 64, FP8 up
-// to 2d = 128) run 8-16 % faster as 4-wave workgroups, three of which share a
-// compute unit, than as 8-wave ones; BF16 with 2d = 128 is 1-2 % faster with
-// 8 waves; one-tile kernels use 8 waves either way.
+// the two-tile kernels of BF16 with 2d = 64 and FP8 with 2d <= 128 run 8-16 %
+// faster as 4-wave workgroups (several share a compute unit) than as 8-wave
+// ones; BF16 with 2d = 128 is 1-2 % faster with 8 waves; one-tile kernels use
+// 8 waves either way.
 int fused_default_tile_rows(int64_t kpad, ipfp_dtype compute) {
   const bool fp8 = compute == IPFP_FP8E4M3;
   if (fp8 ? kpad <= 128 : kpad == 64) return 256;
@@ -1578,6 +1579,93 @@ hipError_t launch_group_fixup(const GroupHalf* g, int count, int per, ipfp_dtype
   else
     hipLaunchKernelGGL(k_group_fixup<false>, dim3(grid), dim3(256), 0, s, g, per);
   return hipGetLastError();
+}
+
+// Workgroups of the sum pass's instantiation for (kpad, type, tile_rows) that
+// one compute unit holds at once (HIP occupancy query, cached; 1 when the
+// query fails, e.g. without a device).
+template <int KP, bool FP8>
+static int pass_wgs_per_cu(int tile_rows) {
+  constexpr int XT = xt_for(KP, FP8);
+  int n = 0;
+  hipError_t e;
+  if (tile_rows >= XT * 256)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, reinterpret_cast<const void*>(&k_fused_pass<KP, XT, 8, FP8, false>), 512, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, reinterpret_cast<const void*>(&k_fused_pass<KP, XT, 4, FP8, false>), 256, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n > 0 ? n : 1;
+}
+
+static int pass_wgs_cached(int64_t kpad, bool fp8, int tile_rows) {
+  static std::atomic<int> cache[2][9][2];
+  const int ki = (int)(kpad / 32), wi = tile_rows >= xt_for((int)kpad, fp8) * 256 ? 1 : 0;
+  if (ki < 1 || ki > 8) return 1;
+  const int hit = cache[fp8][ki][wi].load(std::memory_order_relaxed);
+  if (hit > 0) return hit;
+  int n = 1;
+  if (fp8) {
+    switch (kpad) {
+      case 64: n = pass_wgs_per_cu<64, true>(tile_rows); break;
+      case 128: n = pass_wgs_per_cu<128, true>(tile_rows); break;
+      case 192: n = pass_wgs_per_cu<192, true>(tile_rows); break;
+      case 256: n = pass_wgs_per_cu<256, true>(tile_rows); break;
+      default: break;
+    }
+  } else {
+    switch (kpad) {
+      case 32: n = pass_wgs_per_cu<32, false>(tile_rows); break;
+      case 64: n = pass_wgs_per_cu<64, false>(tile_rows); break;
+      case 96: n = pass_wgs_per_cu<96, false>(tile_rows); break;
+      case 128: n = pass_wgs_per_cu<128, false>(tile_rows); break;
+      case 160: n = pass_wgs_per_cu<160, false>(tile_rows); break;
+      case 192: n = pass_wgs_per_cu<192, false>(tile_rows); break;
+      case 224: n = pass_wgs_per_cu<224, false>(tile_rows); break;
+      case 256: n = pass_wgs_per_cu<256, false>(tile_rows); break;
+      default: break;
+    }
+  }
+  cache[fp8][ki][wi].store(n, std::memory_order_relaxed);
+  return n;
+}
+
+// Split count of a sum pass (R output rows, L reduced rows). Workgroups run
+// in waves of `slots` (compute units x resident workgroups per unit); a
+// workgroup costs its stages plus about one stage of pipeline fill. The count
+// minimises (waves of workgroups) x (stages per workgroup + 1) over 1..64,
+// keeping at least 8 stages per split, the smaller count on ties. It depends
+// only on the market's shape and the device, so results stay reproducible.
+int fused_pass_splits(int64_t R, int64_t L, int64_t kpad, ipfp_dtype compute, int tile_rows) {
+  const bool fp8 = compute == IPFP_FP8E4M3;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  const int64_t slots = (int64_t)cus * pass_wgs_cached(kpad, fp8, tile_rows);
+  const int rows = fused_rows_per_wg(kpad, compute, tile_rows);
+  const int stage = ty_for((int)kpad * (fp8 ? 1 : 2));
+  const int64_t rblocks = (R + rows - 1) / rows;
+  const int64_t T = (L + stage - 1) / stage;
+  int best = 1;
+  int64_t best_cost = INT64_MAX;
+  for (int S = 1; S <= 64; ++S) {
+    if (S > 1 && T / S < 8) break;
+    const int64_t waves = (rblocks * S + slots - 1) / slots;
+    const int64_t cost = waves * ((T + S - 1) / S + 1);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = S;
+    }
+  }
+  return best;
 }
 
 int fused_auto_splits(int64_t R, int64_t L, int rows_per_wg) {

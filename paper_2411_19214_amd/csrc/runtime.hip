@@ -51,8 +51,8 @@ void ipfp::handle_layout(ipfp_handle* h, Carver& cv) {
     h->yshift = cv.take<float>(M);
     const int tr = h->opt.tile_rows > 0 ? h->opt.tile_rows : fused_default_tile_rows(h->kpad, cd);
     const int rx = fused_rows_per_wg(h->kpad, cd, tr);
-    int sx = h->opt.splits > 0 ? h->opt.splits : fused_auto_splits(N, M, rx);
-    int sy = h->opt.splits > 0 ? h->opt.splits : fused_auto_splits(M, N, rx);
+    int sx = h->opt.splits > 0 ? h->opt.splits : fused_pass_splits(N, M, h->kpad, cd, tr);
+    int sy = h->opt.splits > 0 ? h->opt.splits : fused_pass_splits(M, N, h->kpad, cd, tr);
     h->xpart = cv.take<double>((size_t)sx * N);
     h->ypart = cv.take<double>((size_t)sy * M);
     h->xfix = cv.take<int32_t>(N);
@@ -511,8 +511,8 @@ int ipfp_tune(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* opt,
   // split count and its half and double (0 = automatic per pass)
   std::vector<std::pair<int, int>> cand;
   for (int tr : {512, 256}) {
-    const int rows = fused_rows_per_wg(fused_kpad(mk->d, opt->compute), opt->compute, tr);
-    const int sa = fused_auto_splits(mk->N, mk->M, rows);
+    const int sa = fused_pass_splits(mk->N, mk->M, fused_kpad(mk->d, opt->compute),
+                                     opt->compute, tr);
     cand.push_back({tr, 0});
     if (sa / 2 >= 1) cand.push_back({tr, sa / 2});
     if (sa * 2 <= 256) cand.push_back({tr, sa * 2});

@@ -834,11 +834,11 @@ int ipfp_submit(ipfp_server* srv, const ipfp_market* mk, const ipfp_options* opt
   rc = ipfp_footprint(mk, &o, &bytes);
   if (rc != IPFP_OK) return rc;
   if (bytes > srv->arena.cap()) return IPFP_EBUDGET;
-  const int64_t kpad = fused_kpad(mk->d, o.compute);
-  const int rx = fused_rows_per_wg(
-      kpad, o.compute, o.tile_rows > 0 ? o.tile_rows : fused_default_tile_rows(kpad, o.compute));
-  const int sx = o.splits > 0 ? o.splits : fused_auto_splits(mk->N, mk->M, rx);
   if (hipSetDevice(srv->ctx->device) != hipSuccess) return IPFP_EHIP;
+  const int64_t kpad = fused_kpad(mk->d, o.compute);
+  const int tr = o.tile_rows > 0 ? o.tile_rows : fused_default_tile_rows(kpad, o.compute);
+  const int rx = fused_rows_per_wg(kpad, o.compute, tr);
+  const int sx = o.splits > 0 ? o.splits : fused_pass_splits(mk->N, mk->M, kpad, o.compute, tr);
   hipEvent_t ready = nullptr;
   if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return IPFP_EHIP;
   if (hipEventRecord(ready, (hipStream_t)stream) != hipSuccess) {
