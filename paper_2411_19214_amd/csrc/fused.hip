@@ -241,6 +241,17 @@ __device__ __forceinline__ floatx16 mfma_step(const Frag& a, const Frag& b, floa
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
+// Work item of block `bid` in a list of W items ordered split-major (all row
+// blocks of split 0, then split 1, ...). Workgroups are dispatched to the 8
+// XCDs round robin (bid % 8); each XCD takes a contiguous run of the list, so
+// the workgroups it holds at once mostly share a split and stream the same
+// reduced tiles through its own L2. A bijection of [0, W) for every W.
+__device__ __forceinline__ int xcd_item(int bid, int W) {
+  const int per = (W + 7) / 8, rem = W - 8 * (per - 1);   // XCDs g < rem take per
+  const int g = bid & 7, i = bid >> 3;
+  return g <= rem ? g * per + i : rem * per + (g - rem) * (per - 1) + i;
+}
+
 // The reduction pass. MAXMODE: per (split, row) maximum of T over the split
 // (set-up). Otherwise the weighted sum S described at the top of this file.
 //
@@ -290,8 +301,10 @@ __device__ __forceinline__ void fused_pass_body(
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
-  const int split = bid % nsplit;
-  const int rb = bid / nsplit;
+  const int rblocks = (R + WAVES * XT * 32 - 1) / (WAVES * XT * 32);
+  const int item = xcd_item(bid, rblocks * nsplit);
+  const int split = item / rblocks;
+  const int rb = item - split * rblocks;
   const int T = (L + kTY - 1) / kTY;
   const int t0 = split * tiles_per_split;
   const int t1 = min(T, t0 + tiles_per_split);
@@ -642,7 +655,9 @@ __global__ void __launch_bounds__(256)
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
-  const int split = blockIdx.x % nsplit, rb = blockIdx.x / nsplit;
+  const int rblocks = (R + WAVES * 32 - 1) / (WAVES * 32);
+  const int item = xcd_item(blockIdx.x, rblocks * nsplit);
+  const int split = item / rblocks, rb = item - split * rblocks;
   const int T = (L + kTY - 1) / kTY;
   const int t0 = split * tiles_per_split, t1 = min(T, t0 + tiles_per_split);
   const int x = (rb * WAVES + wave) * 32 + l32;
@@ -943,8 +958,10 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
   if (E == INT_MIN) E = 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
-  const int grp = blockIdx.x % ngroups, rest = blockIdx.x / ngroups;
-  const int split = rest % nsplit, rb = rest / nsplit;
+  const int rblocks = (R + WAVES * 32 - 1) / (WAVES * 32);
+  const int item = xcd_item(blockIdx.x, rblocks * nsplit * ngroups);
+  const int unit = item / rblocks, rb = item - unit * rblocks;
+  const int split = unit / ngroups, grp = unit - split * ngroups;
   const int nb0 = grp * NBL, nbn = min(NBL, NB - nb0);
   const int T = (L + kTY - 1) / kTY;
   const int t0 = split * tiles_per_split, t1 = min(T, t0 + tiles_per_split);
