@@ -104,9 +104,11 @@ typedef struct {
   double tol;            /* stop when the row residual < tol; 0 = never       */
   int32_t max_sweeps;    /* >= 1                                              */
   int32_t check_every;   /* >= 1: residual cadence (and host sync cadence)    */
-  int32_t splits;        /* reduction splits per half-sweep; 0 = automatic.
-                            Results are bitwise reproducible for fixed
-                            splits; across splits they agree to rounding.     */
+  int32_t splits;        /* reduction splits per half-sweep; 0 = automatic
+                            (chosen from the shape and the device's compute
+                            units and occupancy). Results are bitwise
+                            reproducible for fixed splits; across splits
+                            they agree to rounding.                           */
   int32_t tile_rows;     /* FUSED: output rows per workgroup (128, 256 or
                             512); 0 = a per-type default (256 for BF16 with
                             2d = 64 and FP8 up to 2d = 128, else 512)         */

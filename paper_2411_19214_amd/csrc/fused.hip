@@ -1685,9 +1685,10 @@ int fused_pass_splits(int64_t R, int64_t L, int64_t kpad, ipfp_dtype compute, in
   return best;
 }
 
+// Split count of the top-k and gradient passes: enough workgroups to fill
+// the 256 CUs several times over, while every split keeps at least 8 staged
+// tiles.
 int fused_auto_splits(int64_t R, int64_t L, int rows_per_wg) {
-  // Enough workgroups to fill the 256 CUs several times over, while every
-  // split keeps at least 8 staged tiles.
   const int64_t rblocks = (R + rows_per_wg - 1) / rows_per_wg;
   const int64_t T = (L + 63) / 64;
   int64_t S = 1;
