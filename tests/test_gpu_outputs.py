@@ -143,3 +143,30 @@ def test_gradient_matches_oracle(torch, lib, N, M, d):
           flush=True)
     assert gx.shape == (N, 2 * d) and gy.shape == (M, 2 * d)
     assert ex < 2e-5 and ey < 2e-5
+
+
+def test_gradient_full_width_sampled(torch, lib):
+    """N = M = 200,000, d = 64 (C3 distribution; many splits, both column
+    groups of the launch): sampled rows and columns against the oracle on the
+    same packed operands, with the bound of the small-size test."""
+    banner("gradient 200k sampled rows and columns")
+    mk = workloads.config_market(3, N=200_000, M=200_000)
+    t = market_tensors(torch, mk)
+    with lib.Market(*t, mk.sigma, max_sweeps=4) as h:
+        h.run(3)
+        a, b, _ = h.read()
+        gx = h.gradient(0).cpu().numpy()
+        gy = h.gradient(1).cpu().numpy()
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    p = float(quant.prescale(mk.sigma))
+    X = quant.packed_rows(np.concatenate([mk.U, mk.Q], 1), mk.sigma, "bf16")
+    Y = quant.packed_rows(np.concatenate([mk.V, mk.P], 1), mk.sigma, "bf16")
+    rng = np.random.default_rng(64)
+    for side, G, A, B, wa, wb in ((0, gx, X, Y, a, b), (1, gy, Y, X, b, a)):
+        rows = rng.choice(A.shape[0], 24, replace=False)
+        mu = O.kernel_from_log2(A[rows] @ B.T) * wa[rows][:, None] * wb[None, :]
+        ref = mu @ (B / p)
+        bound = mu @ np.abs(B / p)
+        err = np.max(np.abs(G[rows] - ref) / bound)
+        print(f"gradient 200k side {side}: max |err| / sum mu|Y| = {err:.2e}", flush=True)
+        assert err < 2e-5
