@@ -175,6 +175,17 @@ struct Vec16<double> {
   static constexpr int n = 2;
 };
 
+// 16 bytes of K. K is read once per pass and is larger than the caches, so
+// the load is marked nontemporal (streaming).
+template <typename TK>
+__device__ __forceinline__ typename Vec16<TK>::T load_k(const TK* p) {
+  typedef TK v16 __attribute__((ext_vector_type(16 / sizeof(TK))));
+  const v16 r = __builtin_nontemporal_load(reinterpret_cast<const v16*>(p));
+  typename Vec16<TK>::T o;
+  __builtin_memcpy(&o, &r, 16);
+  return o;
+}
+
 template <typename TK>
 __device__ __forceinline__ void vec_get(const typename Vec16<TK>::T& v, double* o);
 template <>
@@ -222,7 +233,7 @@ __global__ void __launch_bounds__(256)
     for (int e = 0; e < VN; ++e) vv[e] = v[j + e];
 #pragma unroll
     for (int r = 0; r < kRowsPerWave; ++r) {
-      VT kv = *reinterpret_cast<const VT*>(rp[r] + j);
+      VT kv = load_k<TK>(rp[r] + j);
       double kd[VN];
       vec_get<TK>(kv, kd);
 #pragma unroll
@@ -303,7 +314,7 @@ __global__ void __launch_bounds__(256)
       VT kv[kColRowUnroll];
 #pragma unroll
       for (int q = 0; q < kColRowUnroll; ++q)
-        kv[q] = *reinterpret_cast<const VT*>(K + (x + q) * ldk + y0);
+        kv[q] = load_k<TK>(K + (x + q) * ldk + y0);
 #pragma unroll
       for (int q = 0; q < kColRowUnroll; ++q) {
         double kd[VN];
@@ -314,7 +325,7 @@ __global__ void __launch_bounds__(256)
       }
     }
     for (; x < x1; ++x) {
-      VT kv = *reinterpret_cast<const VT*>(K + x * ldk + y0);
+      VT kv = load_k<TK>(K + x * ldk + y0);
       double kd[VN];
       vec_get<TK>(kv, kd);
       const double w = ut[x];
