@@ -133,6 +133,12 @@ def test_null_arguments(lib):
     assert lib.ipfp_poll(None, 1, None) == _lib.EINVAL
     assert lib.ipfp_cancel(None, 1) == _lib.EINVAL
     assert lib.ipfp_footprint(None, None, None) == _lib.EINVAL
+    # outputs of a resident market: a null handle is refused before any device call
+    assert lib.ipfp_market_topk(None, 0, 10, None, None, None) == _lib.EINVAL
+    assert lib.ipfp_market_gradient(None, 0, None, 128, None) == _lib.EINVAL
+    assert lib.ipfp_market_run(None, 1, None, None) == _lib.EINVAL
+    assert lib.ipfp_stable_factors(None, None, None, None, None, 0, None, 0, None) == _lib.EINVAL
+    assert lib.ipfp_tune(None, None, None, None, None, None) == _lib.EINVAL
 
 
 def test_clock_is_monotonic_ms(lib):
