@@ -171,3 +171,32 @@ def test_gradient_full_width_sampled(torch, lib):
         err = np.max(np.abs(G[rows] - ref) / bound)
         print(f"gradient 200k side {side}: max |err| / sum mu|Y| = {err:.2e}", flush=True)
         assert err < 2e-5
+
+
+def test_output_errors(torch, lib):
+    """Invalid requests for the outputs are refused with IPFP_EINVAL: k outside
+    1..32, a side other than 0 or 1, the gradient of FP8 operands, and top-k or
+    gradient of a plain (materialised-K) market."""
+    banner("output error paths")
+    mk = workloads.factor_market(300, 200, 16, 1.0 / 16, 1.0, "unit", seed=5, name="err")
+    t = market_tensors(torch, mk)
+    with lib.Market(*t, mk.sigma, max_sweeps=3) as h:
+        h.run(2)
+        for call in (lambda: h.topk(0, 0), lambda: h.topk(33, 0), lambda: h.topk(4, 2),
+                     lambda: h.gradient(2)):
+            with pytest.raises(lib.IPFPError) as e:
+                call()
+            assert e.value.code == -1
+        idx, _ = h.topk(4, 1)          # still usable after refused calls
+        assert idx.shape == (200, 4)
+    with lib.Market(*t, mk.sigma, max_sweeps=3, compute="fp8") as h:
+        h.run(1)
+        with pytest.raises(lib.IPFPError) as e:
+            h.gradient(0)
+        assert e.value.code == -1
+    with lib.Market(*t, mk.sigma, max_sweeps=3, path="plain", compute="f32") as h:
+        h.run(1)
+        for call in (lambda: h.topk(4, 0), lambda: h.gradient(0)):
+            with pytest.raises(lib.IPFPError) as e:
+                call()
+            assert e.value.code == -1
