@@ -99,7 +99,7 @@ def s40(v):
     return mp.nstr(v, 40, min_fixed=-mp.inf, max_fixed=mp.inf)
 
 
-def main():
+def main(path=None):
     out = {"source": "eq. 2-5 (Sec. 3.1-3.2), solved by Newton's method in mpmath at 60 digits "
                      "by tests/golden/make_golden.py",
            "markets": []}
@@ -114,7 +114,7 @@ def main():
             "name": name, "phi": phi_s, "n": n_s, "m": m_s, "beta": beta_s,
             "a": [s40(v) for v in a], "b": [s40(v) for v in b],
             "mu": [[s40(v) for v in row] for row in mu], "welfare": s40(W)})
-    with open(os.path.join(HERE, "equilibria.json"), "w") as f:
+    with open(path or os.path.join(HERE, "equilibria.json"), "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
 

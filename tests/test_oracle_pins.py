@@ -489,3 +489,19 @@ def test_golden_equilibria_computed_in_mpmath():
         br = brute.primal_newton(Phi, n, m, beta)
         np.testing.assert_allclose(br.mu, mu, rtol=1e-9, err_msg=mk["name"])
         assert abs(br.value - float(mk["welfare"])) <= 1e-10 * abs(float(mk["welfare"]))
+
+
+def test_golden_file_is_what_its_script_writes(tmp_path):
+    """``tests/golden/equilibria.json`` is exactly the output of its committed
+    generator (mpmath only), so no stored value comes from anywhere else."""
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    spec = importlib.util.spec_from_file_location("make_golden",
+                                                  os.path.join(here, "make_golden.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    out = tmp_path / "equilibria.json"
+    mod.main(str(out))
+    with open(os.path.join(here, "equilibria.json")) as f:
+        assert out.read_text() == f.read()
