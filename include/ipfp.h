@@ -235,7 +235,7 @@ int ipfp_stable_factors(ipfp_ctx *ctx, const ipfp_market *mk, const double *a,
  * float, device) the matching log mu; entries beyond the other side's size
  * are -1 / -inf. Equal scores keep the lower index of a lane's stream, so the
  * order among exact ties is implementation-defined. 1 <= k <= 32. Scratch of
- * splits x rows x (4 + 4) x k' bytes (k' = 8, 16 or 32) is allocated for the
+ * splits x rows x (4 + 4) x k' bytes (k' = 8, 12, 16 or 32) is allocated for the
  * call and charged to the context budget. */
 int ipfp_market_topk(ipfp_handle *h, int side, int32_t k, int32_t *idx_out,
                      float *score_out, void *stream);

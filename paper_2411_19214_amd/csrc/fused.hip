@@ -841,12 +841,14 @@ static hipError_t topk_kp(const FusedPass& fp, const double* a_out, int k, int s
   const int kt = topk_width(k);
   if (kt == 8)
     return topk_t<KP, FP8, 8>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
+  if (kt == 12)
+    return topk_t<KP, FP8, 12>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
   if (kt == 16)
     return topk_t<KP, FP8, 16>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
   return topk_t<KP, FP8, 32>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
 }
 
-int topk_width(int k) { return k <= 8 ? 8 : (k <= 16 ? 16 : 32); }
+int topk_width(int k) { return k <= 8 ? 8 : (k <= 12 ? 12 : (k <= 16 ? 16 : 32)); }
 
 int topk_splits(int64_t R, int64_t L) { return fused_auto_splits(R, L, 128); }
 
