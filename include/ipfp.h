@@ -161,6 +161,27 @@ int ipfp_footprint(const ipfp_market *mk, const ipfp_options *opt,
 int ipfp_solve_market(ipfp_ctx *ctx, const ipfp_market *mk,
                       const ipfp_options *opt, ipfp_result *res, void *stream);
 
+/* Allocation-free variant of ipfp_solve_market, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). It runs the same set-up, sweep kernels
+ * and read-out, so its (a, b), residual history and sweep count equal
+ * ipfp_solve_market's bit for bit, but the market's scratch is carved from a
+ * fixed array of IPFP_NOALLOC_BYTES in device memory that every device the
+ * library runs on holds for the life of the process (its address is looked up
+ * by ipfp_create), and the call allocates nothing: no hipMalloc or hipFree,
+ * no pinned host memory, no events or graphs (opt->use_graph and
+ * opt->time_passes are ignored; loop_ms is host-clock time). The caller still
+ * owns every input and output. A market whose footprint (ipfp_footprint)
+ * exceeds IPFP_NOALLOC_BYTES is refused with IPFP_EBUDGET before any launch.
+ * All calls on one device share that device's array, which keeps the last
+ * call's contents (the set-up initialises everything a solve reads): calls
+ * that overlap on one device, from any thread or stream, race and must be
+ * serialised by the caller. Returns as ipfp_solve_market. */
+#define IPFP_NOALLOC_BYTES ((size_t)64 << 20)
+int ipfp_solve_market_noalloc(ipfp_ctx *ctx, const ipfp_market *mk,
+                              const ipfp_options *opt, ipfp_result *res,
+                              void *stream);
+
 /* Autotuner for the fused path: times whole sweeps of this market (opened on
  * scratch memory, then freed) for 256 and 512 output rows per workgroup and
  * for the automatic reduction-split count, its half and its double, and

@@ -174,8 +174,11 @@ def _info(code, r, hist):
 
 def solve_market(U, Q, V, P, n, m, sigma, tol=0.0, max_sweeps=100, check_every=1,
                  path="fused", compute=None, splits=0, tile_rows=0, b0=None,
-                 use_graph=False, time_passes=False, stream=None, ctx=None):
-    """IPFP on the factor market Phi = U V^T + Q P^T; returns (a, b, info)."""
+                 use_graph=False, time_passes=False, stream=None, ctx=None, no_alloc=False):
+    """IPFP on the factor market Phi = U V^T + Q P^T; returns (a, b, info).
+    ``no_alloc=True`` calls ``ipfp_solve_market_noalloc`` (scratch from the
+    library's fixed per-device array; only the outputs a, b are allocated
+    here, by torch)."""
     torch = _torch()
     if compute is None:
         compute = "bf16" if path == "fused" else "f32"
@@ -194,9 +197,10 @@ def solve_market(U, Q, V, P, n, m, sigma, tol=0.0, max_sweeps=100, check_every=1
     r.res_hist = hist
     r.res_cap = 4096
     ctx = ctx or Context.default(U.device.index or 0)
-    code = _check(library().ipfp_solve_market(ctx.handle, ctypes.byref(mk),
-                                              ctypes.byref(opt), ctypes.byref(r),
-                                              _stream_ptr(stream)), "ipfp_solve_market")
+    fn = library().ipfp_solve_market_noalloc if no_alloc else library().ipfp_solve_market
+    code = _check(fn(ctx.handle, ctypes.byref(mk), ctypes.byref(opt), ctypes.byref(r),
+                     _stream_ptr(stream)),
+                  "ipfp_solve_market_noalloc" if no_alloc else "ipfp_solve_market")
     return a, b, _info(code, r, hist)
 
 

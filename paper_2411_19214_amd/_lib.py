@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libipfp.so")
 
 F64, F32, BF16, FP8E4M3 = 0, 1, 2, 3
 PATH_FUSED, PATH_PLAIN = 0, 1
+NOALLOC_BYTES = 64 << 20     # IPFP_NOALLOC_BYTES
 
 OK, NOT_CONVERGED = 0, 1
 EINVAL, EBUDGET, EHIP, ENONFINITE, ECANCELLED, EBUSY, ENOTFOUND = -1, -2, -3, -4, -5, -6, -7
@@ -93,6 +94,9 @@ SIGNATURES = {
     "ipfp_solve_market": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Market),
                                          ctypes.POINTER(Options), ctypes.POINTER(Result),
                                          ctypes.c_void_p]),
+    "ipfp_solve_market_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Market),
+                                                 ctypes.POINTER(Options),
+                                                 ctypes.POINTER(Result), ctypes.c_void_p]),
     "ipfp_solve_market_phi": (ctypes.c_int, [
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
         ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,

@@ -71,6 +71,8 @@ hipError_t launch_check(Ctl* ctl, const double* res_block, int nblocks,
                         double* hist, SweepParams sp, hipStream_t s);
 hipError_t launch_init_vec(double* v, const double* src, int64_t len,
                            hipStream_t s);
+// Zero `bytes` (rounded up to whole 32-bit words) of device memory.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_validate_margins(const double* n, int64_t N, const double* m,
                                    int64_t M, Ctl* ctl, hipStream_t s);
 hipError_t launch_mu_pairs(const void* U, const void* Q, const void* V,

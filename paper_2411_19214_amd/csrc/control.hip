@@ -82,6 +82,22 @@ hipError_t launch_check(Ctl* ctl, const double* res_block, int nblocks,
   return hipGetLastError();
 }
 
+// Zero fill of `words` 32-bit words (control blocks and other small scratch
+// that must start at zero; a kernel rather than a memset node, so that the
+// set-up can sit inside a captured graph).
+__global__ void k_zero_words(int32_t* p, int64_t words) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words) p[i] = 0;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t words = (int64_t)((bytes + 3) / 4);
+  if (words == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s,
+                     static_cast<int32_t*>(p), words);
+  return hipGetLastError();
+}
+
 __global__ void k_init_vec(double* v, const double* src, int64_t len) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) v[i] = src ? src[i] : 1.0;

@@ -13,6 +13,8 @@ struct ipfp_ctx {
   size_t budget;
   size_t used;
   std::mutex mu;
+  void* noalloc = nullptr;  // device address of the allocation-free solve's
+                            // scratch array on this context's device
 };
 
 namespace ipfp {

@@ -13,6 +13,43 @@
 
 using namespace ipfp;
 
+// Scratch of the allocation-free solve (ipfp_solve_market_noalloc): one array
+// in device memory, a copy of which every device the library runs on holds
+// until the process ends. In host code this name is only a handle for the
+// symbol lookup below, never an address: the array's device address is
+// looked up once per device (with that device current) and kept in
+// g_noalloc, and only that address is passed to kernels.
+static __device__ __align__(256) char scratch[IPFP_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void* g_noalloc[kMaxDevices];
+std::mutex g_noalloc_mu;
+
+// The device address of `scratch` on device `dev` (looked up on first use).
+int noalloc_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return IPFP_EINVAL;
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  if (!g_noalloc[dev]) {
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return IPFP_EHIP;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return IPFP_EHIP;
+    }
+    g_noalloc[dev] = p;
+  }
+  *out = g_noalloc[dev];
+  return IPFP_OK;
+}
+}  // namespace
+
 #define HIPCHK(expr)                         \
   do {                                       \
     hipError_t e_ = (expr);                  \
@@ -208,7 +245,7 @@ hipError_t ipfp::handle_setup(ipfp_handle* h, const void* phi, ipfp_dtype phi_dt
                               int64_t ld_phi, hipStream_t s) {
   const ipfp_market* mk = &h->mk;
   const ipfp_options* opt = &h->opt;
-  TRY(hipMemsetAsync(h->ctl, 0, sizeof(Ctl), s));
+  TRY(launch_zero(h->ctl, sizeof(Ctl), s));
   TRY(launch_validate_margins(mk->n, h->N, mk->m, h->M, h->ctl, s));
   TRY(launch_init_vec(h->u2, nullptr, 2 * h->N, s));
   TRY(launch_init_vec(h->v, opt->b0, h->M, s));
@@ -283,10 +320,14 @@ int ipfp_create(ipfp_ctx** out, int hip_device, size_t hbm_budget_bytes) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n)
     return IPFP_EINVAL;
+  void* sp = nullptr;
+  const int rc = noalloc_scratch(hip_device, &sp);
+  if (rc != IPFP_OK) return rc;
   ipfp_ctx* c = new ipfp_ctx;
   c->device = hip_device;
   c->budget = hbm_budget_bytes;
   c->used = 0;
+  c->noalloc = sp;
   *out = c;
   return IPFP_OK;
 }
@@ -497,6 +538,64 @@ int ipfp_solve_market(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* 
   if (rc != IPFP_OK) return rc;
   rc = solve_handle(h, res, (hipStream_t)stream);
   destroy_handle(h);
+  return rc;
+}
+
+// The one-call solve on the per-device scratch array: the same set-up, sweep
+// kernels and read-out as ipfp_solve_market (so the same results, bit for
+// bit), with the handle on the stack, the control block read into host stack
+// memory and the loop timed on the host clock. Nothing is allocated.
+int ipfp_solve_market_noalloc(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* opt,
+                              ipfp_result* res, void* stream) {
+  if (!ctx || !res || !res->a || !res->b) return IPFP_EINVAL;
+  int rc = validate_market(mk, opt, true);
+  if (rc != IPFP_OK) return rc;
+  if (!ctx->noalloc) return IPFP_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  ipfp_handle h;
+  h.ctx = ctx;
+  h.mk = *mk;
+  h.opt = *opt;
+  h.opt.use_graph = 0;
+  h.opt.time_passes = 0;
+  h.plain = opt->path == IPFP_PATH_PLAIN;
+  h.N = mk->N;
+  h.M = mk->M;
+  h.kdt = opt->compute == IPFP_F64 ? IPFP_F64 : IPFP_F32;
+  h.arena = true;   // the memory is not the handle's
+  Carver cv;
+  handle_layout(&h, cv);
+  h.bytes = align_up(cv.off, 256);
+  if (h.bytes > (size_t)IPFP_NOALLOC_BYTES) return IPFP_EBUDGET;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IPFP_EHIP;
+  const double t0 = now_ms();
+  h.mem = static_cast<char*>(ctx->noalloc);
+  Carver real;
+  real.base = h.mem;
+  handle_layout(&h, real);
+  Ctl hc{};
+  h.host_ctl = &hc;
+  if (handle_setup(&h, nullptr, IPFP_F32, 0, s) != hipSuccess) return IPFP_EHIP;
+  if (read_ctl(&h, s) != IPFP_OK) return IPFP_EHIP;
+  if (hc.bad_margin) return IPFP_EINVAL;
+  if (hc.nonfinite) return IPFP_ENONFINITE;
+  h.setup_ms = now_ms() - t0;
+  const int total = h.opt.max_sweeps + 1;   // +1: final residual row pass
+  const int chunk = std::max(h.opt.check_every, 8);
+  const double t1 = now_ms();
+  for (bool done = false; !done;) {
+    const int todo = std::min(chunk, total - h.units);
+    for (int k = 0; k < todo; ++k) {
+      if (enqueue_unit(&h, s, false) != hipSuccess) return IPFP_EHIP;
+      h.units += 1;
+    }
+    if (read_ctl(&h, s) != IPFP_OK) return IPFP_EHIP;
+    if (hc.nonfinite) return IPFP_ENONFINITE;
+    done = hc.done || h.units >= total;
+  }
+  h.loop_ms = now_ms() - t1;
+  rc = ipfp_market_read(&h, res->a, res->b, res, stream);
+  h.host_ctl = nullptr;
   return rc;
 }
 

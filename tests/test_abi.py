@@ -141,6 +141,13 @@ def test_null_arguments(lib):
     assert lib.ipfp_tune(None, None, None, None, None, None) == _lib.EINVAL
 
 
+def test_noalloc_capacity_matches_the_header(lib):
+    text = open(HEADER).read()
+    m = re.search(r"#define IPFP_NOALLOC_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_BYTES
+    assert lib.ipfp_solve_market_noalloc(None, None, None, None, None) == _lib.EINVAL
+
+
 def test_clock_is_monotonic_ms(lib):
     import time
     a = lib.ipfp_clock_ms()
