@@ -53,13 +53,13 @@
 extern "C" {
 #endif
 
-#define IPFP_ABI_VERSION 1
+#define IPFP_ABI_VERSION 2
 
 typedef enum {
   IPFP_F64 = 0,      /* IEEE binary64 */
   IPFP_F32 = 1,      /* IEEE binary32 */
   IPFP_BF16 = 2,     /* bfloat16 (upper half of binary32) */
-  IPFP_FP8E4M3 = 3   /* OCP FP8 e4m3fn with a power-of-two scale per row */
+  IPFP_FP8E4M3 = 3   /* OCP FP8 e4m3fn codes with a power-of-two scale per row */
 } ipfp_dtype;
 
 typedef enum {
@@ -84,8 +84,16 @@ typedef struct ipfp_handle ipfp_handle; /* a market held resident on device */
 
 /* A market given by its factors (eq. 8): Phi = U V^T + Q P^T.
  * U, Q: N x d device matrices with row stride ld_x; V, P: M x d with ld_y.
- * All four have dtype `in_dtype` (F64, F32 or BF16). n (N) and m (M) are
- * device FP64 margins. */
+ * All four have dtype `in_dtype` (F64, F32, BF16 or FP8E4M3). n (N) and m (M)
+ * are device FP64 margins.
+ * FP8E4M3 input: the factors hold 1-byte OCP e4m3fn codes and the value of
+ * row x's entries is code value x scale_x[x] (one scale per concatenated row
+ * [U|Q]_x), of row y's entries code value x scale_y[y] ([V|P]_y). scale_x
+ * (N) and scale_y (M) are device FP32 arrays, required for FP8 input and not
+ * read otherwise; every scale must be a positive normal power of two, so the
+ * values are exact in FP32 (checked on the device; a violation gives
+ * IPFP_EINVAL). Such a market solves exactly as the same values given in
+ * FP32 would (bitwise, for every path and compute type). */
 typedef struct {
   int64_t N, M, d;
   ipfp_dtype in_dtype;
@@ -93,14 +101,17 @@ typedef struct {
   int64_t ld_x, ld_y;
   const double *n, *m;
   double sigma;
+  const float *scale_x, *scale_y;
 } ipfp_market;
 
 typedef struct {
   ipfp_path path;        /* FUSED (factors) or PLAIN (materialised K)         */
-  ipfp_dtype compute;    /* FUSED: BF16 or FP8E4M3 operands for the surplus
-                            tiles (FP32 accumulate, FP32 exp2, FP64 sums and
-                            updates). PLAIN: F32 or F64 storage of K (FP64
-                            sums and updates either way).                     */
+  ipfp_dtype compute;    /* FUSED: BF16, FP8E4M3 or F32 operands for the
+                            surplus tiles (BF16 and FP8 on their MFMAs, F32 on
+                            the FP32 MFMA v_mfma_f32_32x32x2_f32; FP32
+                            accumulate, FP32 exp2, FP64 sums and updates).
+                            PLAIN: F32 or F64 storage of K (FP64 sums and
+                            updates either way).                              */
   double tol;            /* stop when the row residual < tol; 0 = never       */
   int32_t max_sweeps;    /* >= 1                                              */
   int32_t check_every;   /* >= 1: residual cadence (and host sync cadence)    */
@@ -111,7 +122,9 @@ typedef struct {
                             they agree to rounding.                           */
   int32_t tile_rows;     /* FUSED: output rows per workgroup (128, 256 or
                             512); 0 = a per-type default (256 for BF16 with
-                            2d = 64 and FP8 up to 2d = 128, else 512)         */
+                            2d = 64 and FP8 up to 2d = 128, else 512). F32
+                            compute always uses 128 (one tile of 32 rows per
+                            wave, four waves)                                 */
   const double *b0;      /* optional device warm start for v (length M);
                             NULL = ones. The initial u is never read.         */
   int32_t use_graph;     /* 1 = replay sweeps through a captured hipGraph     */
@@ -284,13 +297,15 @@ int ipfp_market_gradient(ipfp_handle *h, int side, double *g_out, int64_t ld_g,
  * input to FP32. BF16: 2-byte codes of the round-to-nearest-even value.
  * FP8E4M3: 1-byte e4m3fn codes of p x / s, with one FP32 power-of-two scale
  * s per row (the smallest with max |p x| <= 448 s) written to `scale_out`.
- * `out` is a device buffer of rows * kpad codes; kpad is returned through
- * *kpad_out (pass out = NULL to query it). The solver packs with the market's
+ * F32: the FP32 values p x. `out` is a device buffer of rows * kpad codes
+ * (values for F32); kpad is returned through *kpad_out (pass out = NULL to
+ * query it). FP8E4M3 input takes its per-row scales from `in_scale` (as
+ * ipfp_market's scale_x; NULL otherwise). The solver packs with the market's
  * sigma, so this reproduces its operands bit for bit. */
 int ipfp_pack_side(ipfp_ctx *ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
-                   const void *A, const void *B, int64_t ld, ipfp_dtype compute,
-                   double sigma, void *out, float *scale_out, int64_t *kpad_out,
-                   void *stream);
+                   const void *A, const void *B, const float *in_scale, int64_t ld,
+                   ipfp_dtype compute, double sigma, void *out, float *scale_out,
+                   int64_t *kpad_out, void *stream);
 
 /* ---- serving: continuous batching of many markets ------------------------
  *

@@ -24,9 +24,13 @@ quantised values, produced here independently of the GPU's packing code.
   log2 units, T = Phi log2(e) / (2 sigma), and K = 2^T. ``packed_rows``
   reproduces those operand values; with them the oracle computes K = 2^T.
 
+* FP32 operands (the fused path's FP32 mode) are the FP32 products p x; no
+  further rounding.
+
 Parity status: pinned in the test suite against brute-force nearest-value
 search over every BF16 / e4m3 code; ``packed_rows`` against the GPU packing
-bit for bit and, with p = 1, against the plain rounding functions.
+bit for bit and, with p = 1, against the plain rounding functions; its FP32
+values against the exact (FP64) product rounded once to FP32.
 """
 from __future__ import annotations
 
@@ -127,9 +131,12 @@ def prescale(sigma: float) -> np.float32:
 
 
 def packed_rows(rows, sigma: float, compute: str) -> np.ndarray:
-    """FP64 values of the fused path's operand rows p [A|B] ("bf16" or "fp8"):
-    the input is rounded to FP32, multiplied by p in FP32, then rounded."""
+    """FP64 values of the fused path's operand rows p [A|B] ("bf16", "fp8" or
+    "f32"): the input is rounded to FP32, multiplied by p in FP32, then
+    rounded to the operand type ("f32": no further rounding)."""
     x = np.asarray(rows, dtype=np.float32) * prescale(sigma)
+    if compute == "f32":
+        return x.astype(np.float64)
     if compute == "bf16":
         return bf16_round(x).astype(np.float64)
     q, _ = e4m3_quantize_rows(x.astype(np.float64))

@@ -59,7 +59,21 @@ def _dtype_code(t) -> int:
         return _lib.F32
     if t.dtype == torch.bfloat16:
         return _lib.BF16
+    if t.dtype == torch.float8_e4m3fn:
+        return _lib.FP8E4M3
     raise TypeError(f"unsupported factor dtype {t.dtype}")
+
+
+def _row_scales(scale, rows, name):
+    """Device FP32 per-row scales of FP8 factors (checked here for shape and
+    type; the library checks that each is a power of two)."""
+    torch = _torch()
+    if scale is None:
+        raise ValueError(f"FP8 factors need {name} (FP32 per-row power-of-two scales)")
+    _dev(scale, name)
+    if scale.dtype != torch.float32 or scale.shape != (rows,) or not scale.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 vector of length {rows}")
+    return scale.data_ptr()
 
 
 def _stream_ptr(stream):
@@ -117,7 +131,7 @@ class SolveInfo:
         return self.status == _lib.OK
 
 
-def _market_struct(U, Q, V, P, n, m, sigma):
+def _market_struct(U, Q, V, P, n, m, sigma, scale_x=None, scale_y=None):
     for t, nm in ((U, "U"), (Q, "Q"), (V, "V"), (P, "P"), (n, "n"), (m, "m")):
         _dev(t, nm)
     torch = _torch()
@@ -146,6 +160,9 @@ def _market_struct(U, Q, V, P, n, m, sigma):
     mk.ld_x, mk.ld_y = U.stride(0), V.stride(0)
     mk.n, mk.m = n.data_ptr(), m.data_ptr()
     mk.sigma = float(sigma)
+    if dt == _lib.FP8E4M3:
+        mk.scale_x = _row_scales(scale_x, N, "scale_x")
+        mk.scale_y = _row_scales(scale_y, M, "scale_y")
     return mk
 
 
@@ -174,15 +191,19 @@ def _info(code, r, hist):
 
 def solve_market(U, Q, V, P, n, m, sigma, tol=0.0, max_sweeps=100, check_every=1,
                  path="fused", compute=None, splits=0, tile_rows=0, b0=None,
-                 use_graph=False, time_passes=False, stream=None, ctx=None, no_alloc=False):
+                 use_graph=False, time_passes=False, stream=None, ctx=None, no_alloc=False,
+                 scale_x=None, scale_y=None):
     """IPFP on the factor market Phi = U V^T + Q P^T; returns (a, b, info).
+    ``compute`` is "bf16", "fp8" or "f32" on the fused path, "f32" or "f64"
+    (storage of K) on the plain path. FP8 factors (torch.float8_e4m3fn codes)
+    take per-row power-of-two scales ``scale_x`` (N) and ``scale_y`` (M).
     ``no_alloc=True`` calls ``ipfp_solve_market_noalloc`` (scratch from the
     library's fixed per-device array; only the outputs a, b are allocated
     here, by torch)."""
     torch = _torch()
     if compute is None:
         compute = "bf16" if path == "fused" else "f32"
-    mk = _market_struct(U, Q, V, P, n, m, sigma)
+    mk = _market_struct(U, Q, V, P, n, m, sigma, scale_x, scale_y)
     if b0 is not None:
         _dev(b0, "b0")
         if b0.dtype != torch.float64 or b0.shape != (mk.M,):
@@ -240,11 +261,13 @@ class Market:
 
     def __init__(self, U, Q, V, P, n, m, sigma, tol=0.0, max_sweeps=100,
                  check_every=1, path="fused", compute=None, splits=0, tile_rows=0,
-                 b0=None, use_graph=False, time_passes=False, stream=None, ctx=None):
+                 b0=None, use_graph=False, time_passes=False, stream=None, ctx=None,
+                 scale_x=None, scale_y=None):
         if compute is None:
             compute = "bf16" if path == "fused" else "f32"
-        self._keep = (U, Q, V, P, n, m, b0)  # the library reads these buffers
-        self._mk = _market_struct(U, Q, V, P, n, m, sigma)
+        # the library reads these buffers until close()
+        self._keep = (U, Q, V, P, n, m, b0, scale_x, scale_y)
+        self._mk = _market_struct(U, Q, V, P, n, m, sigma, scale_x, scale_y)
         self._opt = _options(path, compute, tol, max_sweeps, check_every, splits,
                              tile_rows, b0, use_graph, time_passes)
         self.ctx = ctx or Context.default(U.device.index or 0)
@@ -321,12 +344,13 @@ class Market:
         self.close()
 
 
-def mu_pairs(U, Q, V, P, sigma, a, b, xs, ys, stream=None, ctx=None):
+def mu_pairs(U, Q, V, P, sigma, a, b, xs, ys, stream=None, ctx=None, scale_x=None,
+             scale_y=None):
     """mu at requested (x, y) pairs: exp(Phi_xy / 2 sigma) a_x b_y (eq. 4)."""
     torch = _torch()
     n_dummy = torch.ones(U.shape[0], dtype=torch.float64, device=U.device)
     m_dummy = torch.ones(V.shape[0], dtype=torch.float64, device=U.device)
-    mk = _market_struct(U, Q, V, P, n_dummy, m_dummy, sigma)
+    mk = _market_struct(U, Q, V, P, n_dummy, m_dummy, sigma, scale_x, scale_y)
     xs = xs.to(device=U.device, dtype=torch.int64).contiguous()
     ys = ys.to(device=U.device, dtype=torch.int64).contiguous()
     out = torch.empty(xs.numel(), dtype=torch.float64, device=U.device)
@@ -337,12 +361,13 @@ def mu_pairs(U, Q, V, P, sigma, a, b, xs, ys, stream=None, ctx=None):
     return out
 
 
-def stable_factors(U, Q, V, P, sigma, a, b, stream=None, ctx=None):
+def stable_factors(U, Q, V, P, sigma, a, b, stream=None, ctx=None, scale_x=None,
+                   scale_y=None):
     """(psi, xi) of eq. 11: log mu_xy = <psi_x, xi_y> / (2 sigma), FP64."""
     torch = _torch()
     n_dummy = torch.ones(U.shape[0], dtype=torch.float64, device=U.device)
     m_dummy = torch.ones(V.shape[0], dtype=torch.float64, device=U.device)
-    mk = _market_struct(U, Q, V, P, n_dummy, m_dummy, sigma)
+    mk = _market_struct(U, Q, V, P, n_dummy, m_dummy, sigma, scale_x, scale_y)
     w = 2 * mk.d + 2
     psi = torch.empty((mk.N, w), dtype=torch.float64, device=U.device)
     xi = torch.empty((mk.M, w), dtype=torch.float64, device=U.device)
@@ -353,27 +378,32 @@ def stable_factors(U, Q, V, P, sigma, a, b, stream=None, ctx=None):
     return psi, xi
 
 
-def pack_side(A, B, compute="bf16", sigma=0.0, stream=None, ctx=None):
+def pack_side(A, B, compute="bf16", sigma=0.0, stream=None, ctx=None, in_scale=None):
     """The fused path's packed operand of one side: (codes, scales or None),
     prescaled by sqrt(log2(e) / (2 sigma)) as the solver does (no prescale for
     sigma = 0). BF16 codes come back as int16 (bit patterns), FP8 codes as
-    uint8."""
+    uint8, FP32 values as float32. FP8 input (float8_e4m3fn codes) takes its
+    per-row scales from ``in_scale``."""
     torch = _torch()
     rows, d = A.shape
     kpad = ctypes.c_int64()
     ctx = ctx or Context.default(A.device.index or 0)
     lib = library()
-    _check(lib.ipfp_pack_side(ctx.handle, rows, d, _dtype_code(A), None, None, A.stride(0),
+    dt = _dtype_code(A)
+    isc = _row_scales(in_scale, rows, "in_scale") if dt == _lib.FP8E4M3 else None
+    _check(lib.ipfp_pack_side(ctx.handle, rows, d, dt, None, None, None, A.stride(0),
                               _DT[compute], float(sigma), None, None, ctypes.byref(kpad),
                               None),
            "ipfp_pack_side")
+    scale = None
     if compute == "bf16":
         out = torch.empty((rows, kpad.value), dtype=torch.int16, device=A.device)
-        scale = None
+    elif compute == "f32":
+        out = torch.empty((rows, kpad.value), dtype=torch.float32, device=A.device)
     else:
         out = torch.empty((rows, kpad.value), dtype=torch.uint8, device=A.device)
         scale = torch.empty(rows, dtype=torch.float32, device=A.device)
-    _check(lib.ipfp_pack_side(ctx.handle, rows, d, _dtype_code(A), A.data_ptr(), B.data_ptr(),
+    _check(lib.ipfp_pack_side(ctx.handle, rows, d, dt, A.data_ptr(), B.data_ptr(), isc,
                               A.stride(0), _DT[compute], float(sigma), out.data_ptr(),
                               scale.data_ptr() if scale is not None else None,
                               ctypes.byref(kpad), _stream_ptr(stream)), "ipfp_pack_side")
@@ -453,9 +483,9 @@ class Server:
         self._live = {}     # ticket -> (request, buffers the library uses)
 
     def submit(self, U, Q, V, P, n, m, sigma, tol=1e-6, max_sweeps=100, check_every=1,
-               splits=0, b0=None, stream=None) -> Request:
+               splits=0, b0=None, stream=None, scale_x=None, scale_y=None) -> Request:
         torch = _torch()
-        mk = _market_struct(U, Q, V, P, n, m, sigma)
+        mk = _market_struct(U, Q, V, P, n, m, sigma, scale_x, scale_y)
         opt = _options("fused", self.compute, tol, max_sweeps, check_every, splits, 0, b0,
                        False, False)
         a = torch.empty(mk.N, dtype=torch.float64, device=U.device)
@@ -470,7 +500,8 @@ class Server:
                                      ctypes.byref(r), ctypes.byref(t), _stream_ptr(stream)),
                "ipfp_submit")
         req = Request(t.value, a, b, mk.N, mk.M)
-        self._live[t.value] = (req, (U, Q, V, P, n, m, b0, mk, opt, r, hist))
+        self._live[t.value] = (req, (U, Q, V, P, n, m, b0, mk, opt, r, hist, scale_x,
+                                     scale_y))
         return req
 
     def _update(self, req, code, info):

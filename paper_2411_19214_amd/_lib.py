@@ -26,6 +26,7 @@ class Market(ctypes.Structure):
         ("ld_x", ctypes.c_int64), ("ld_y", ctypes.c_int64),
         ("n", ctypes.c_void_p), ("m", ctypes.c_void_p),
         ("sigma", ctypes.c_double),
+        ("scale_x", ctypes.c_void_p), ("scale_y", ctypes.c_void_p),
     ]
 
 
@@ -115,8 +116,8 @@ SIGNATURES = {
         ctypes.c_void_p]),
     "ipfp_pack_side": (ctypes.c_int, [
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
-        ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
-        ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "ipfp_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Market),
                                  ctypes.POINTER(Options), ctypes.POINTER(Options),
                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),

@@ -18,7 +18,8 @@ struct Ctl {
   int32_t stop_sweep;   // sweep index of the returned state
   int32_t n_checks;     // residual checks recorded so far
   int32_t nonfinite;    // 1 if a non-finite intermediate was produced
-  int32_t bad_margin;   // 1 if a margin was not > 0 and finite
+  int32_t bad_margin;   // 1 if a margin was not > 0 and finite, or an FP8
+                        // input row scale not a positive power of two
   int32_t fix_rows;     // rows queued for the exact-shift fallback (this pass)
   int32_t fix_total;    // rows recomputed by the fallback over the solve
   int32_t wexp[2];      // fused path: largest binary exponent of u (0), v (1)
@@ -43,6 +44,22 @@ __device__ __forceinline__ double quad_root(double marg, double s) {
 // True when sweep i's state gets a residual check.
 __device__ __forceinline__ bool is_check(int i, const SweepParams& sp) {
   return i >= 1 && (i % sp.check_every == 0 || i == sp.max_sweeps);
+}
+
+// Value of an OCP e4m3fn code (1 sign, 4 exponent bits with bias 7, 3
+// significand bits; subnormals (f/8) 2^-6; the NaN codes 0x7F / 0xFF are
+// decoded as 480 and never produced by the packer).
+__device__ __forceinline__ float e4m3_val(uint8_t c) {
+  const int e = (c >> 3) & 0xF, f = c & 7;
+  const float v = e == 0 ? ldexpf((float)f, -9) : ldexpf((float)(8 + f), e - 10);
+  return (c & 0x80) ? -v : v;
+}
+
+// A row scale of FP8 input: a positive, normal power of two.
+__device__ __forceinline__ bool pow2_scale_ok(float s) {
+  const uint32_t b = __float_as_uint(s);
+  return (b >> 31) == 0 && (b & 0x7FFFFFu) == 0 && ((b >> 23) & 0xFF) != 0 &&
+         ((b >> 23) & 0xFF) != 0xFF;
 }
 
 constexpr int kWave = 64;
@@ -75,8 +92,11 @@ hipError_t launch_init_vec(double* v, const double* src, int64_t len,
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_validate_margins(const double* n, int64_t N, const double* m,
                                    int64_t M, Ctl* ctl, hipStream_t s);
+hipError_t launch_validate_scales(const float* sx, int64_t N, const float* sy, int64_t M,
+                                  Ctl* ctl, hipStream_t s);
 hipError_t launch_mu_pairs(const void* U, const void* Q, const void* V,
-                           const void* P, ipfp_dtype dt, int64_t ld_x,
+                           const void* P, ipfp_dtype dt, const float* scale_x,
+                           const float* scale_y, int64_t ld_x,
                            int64_t ld_y, int64_t N, int64_t M, int64_t d,
                            double sigma, const double* a, const double* b,
                            const int64_t* xs, const int64_t* ys, int64_t count,
@@ -84,7 +104,8 @@ hipError_t launch_mu_pairs(const void* U, const void* Q, const void* V,
 
 // plain path (plain.hip)
 hipError_t launch_phi_from_factors(const void* U, const void* Q, const void* V,
-                                   const void* P, ipfp_dtype dt, int64_t ld_x,
+                                   const void* P, ipfp_dtype dt, const float* scale_x,
+                                   const float* scale_y, int64_t ld_x,
                                    int64_t ld_y, int64_t N, int64_t M,
                                    int64_t d, void* Kbuf, ipfp_dtype kdt,
                                    int64_t ldk, hipStream_t s);
@@ -112,7 +133,7 @@ struct FusedSide {
 int64_t fused_kpad(int64_t d, ipfp_dtype compute);
 float fused_prescale(double sigma);
 hipError_t launch_pack(const void* A, const void* B, ipfp_dtype in_dt,
-                       int64_t ld, int64_t rows, int64_t d, ipfp_dtype compute,
+                       const float* in_scale, int64_t ld, int64_t rows, int64_t d, ipfp_dtype compute,
                        int64_t kpad, float prescale, void* out, float* scale,
                        Ctl* ctl, hipStream_t s);
 
@@ -159,7 +180,8 @@ size_t gradient_scratch_bytes(int kpad, int64_t L);
 hipError_t launch_gradient(const FusedPass& fp, const int* Eptr, const double* a_out,
                            double inv_p, int splits, double* gpart, uint16_t* yt, int width,
                            double* g, int64_t ld_g, hipStream_t s);
-hipError_t launch_stable_factors(const void* A, const void* B, ipfp_dtype dt, int64_t ld,
+hipError_t launch_stable_factors(const void* A, const void* B, ipfp_dtype dt,
+                                 const float* in_scale, int64_t ld,
                                  int64_t rows, int64_t d, double sigma, const double* w,
                                  int log_col, double* out, int64_t ld_out, hipStream_t s);
 

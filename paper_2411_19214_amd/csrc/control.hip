@@ -119,6 +119,21 @@ __global__ void k_validate(const double* a, int64_t len, Ctl* ctl) {
   }
 }
 
+// FP8 input: every row scale must be a positive, normal power of two.
+__global__ void k_validate_scales(const float* s, int64_t len, Ctl* ctl) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len && !pow2_scale_ok(s[i])) atomicOr(&ctl->bad_margin, 1);
+}
+
+hipError_t launch_validate_scales(const float* sx, int64_t N, const float* sy, int64_t M,
+                                  Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate_scales, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                     sx, N, ctl);
+  hipLaunchKernelGGL(k_validate_scales, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s,
+                     sy, M, ctl);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate_margins(const double* n, int64_t N, const double* m,
                                    int64_t M, Ctl* ctl, hipStream_t s) {
   hipLaunchKernelGGL(k_validate, dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
@@ -140,6 +155,8 @@ __device__ __forceinline__ double ld_elem(const void* p, int64_t i,
       return static_cast<const double*>(p)[i];
     case IPFP_F32:
       return (double)static_cast<const float*>(p)[i];
+    case IPFP_FP8E4M3:   // code value; the caller applies the row scale
+      return (double)e4m3_val(static_cast<const uint8_t*>(p)[i]);
     default: {  // BF16 codes
       uint32_t bits = (uint32_t)static_cast<const uint16_t*>(p)[i] << 16;
       return (double)__uint_as_float(bits);
@@ -154,18 +171,20 @@ __device__ __forceinline__ double ld_elem(const void* p, int64_t i,
 // the other (2 sigma, not the printed sigma: with w = sqrt of the unmatched
 // mass this is sigma log mu_x0, which makes the inner product reproduce
 // eq. 4).
-__global__ void k_stable_factors(const void* A, const void* B, ipfp_dtype dt, int64_t ld,
+__global__ void k_stable_factors(const void* A, const void* B, ipfp_dtype dt,
+                                 const float* in_scale, int64_t ld,
                                  int64_t rows, int64_t d, double sigma, const double* w,
                                  int log_col, double* out, int64_t ld_out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t width = 2 * d + 2;
   if (i >= rows * width) return;
   const int64_t r = i / width, c = i % width;
+  const double rs = dt == IPFP_FP8E4M3 ? (double)in_scale[r] : 1.0;
   double v;
   if (c < d) {
-    v = ld_elem(A, r * ld + c, dt);
+    v = ld_elem(A, r * ld + c, dt) * rs;
   } else if (c < 2 * d) {
-    v = ld_elem(B, r * ld + (c - d), dt);
+    v = ld_elem(B, r * ld + (c - d), dt) * rs;
   } else if (c - 2 * d == log_col) {
     v = 2.0 * sigma * log(w[r]);
   } else {
@@ -174,17 +193,19 @@ __global__ void k_stable_factors(const void* A, const void* B, ipfp_dtype dt, in
   out[r * ld_out + c] = v;
 }
 
-hipError_t launch_stable_factors(const void* A, const void* B, ipfp_dtype dt, int64_t ld,
+hipError_t launch_stable_factors(const void* A, const void* B, ipfp_dtype dt,
+                                 const float* in_scale, int64_t ld,
                                  int64_t rows, int64_t d, double sigma, const double* w,
                                  int log_col, double* out, int64_t ld_out, hipStream_t s) {
   const int64_t n = rows * (2 * d + 2);
   hipLaunchKernelGGL(k_stable_factors, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                     A, B, dt, ld, rows, d, sigma, w, log_col, out, ld_out);
+                     A, B, dt, in_scale, ld, rows, d, sigma, w, log_col, out, ld_out);
   return hipGetLastError();
 }
 
 __global__ void k_mu_pairs(const void* U, const void* Q, const void* V,
-                           const void* P, ipfp_dtype dt, int64_t ld_x,
+                           const void* P, ipfp_dtype dt, const float* scale_x,
+                           const float* scale_y, int64_t ld_x,
                            int64_t ld_y, int64_t N, int64_t M, int64_t d,
                            double sigma, const double* a, const double* b,
                            const int64_t* xs, const int64_t* ys, int64_t count,
@@ -202,19 +223,22 @@ __global__ void k_mu_pairs(const void* U, const void* Q, const void* V,
     phi = fma(ld_elem(U, x * ld_x + k, dt), ld_elem(V, y * ld_y + k, dt), phi);
     phi = fma(ld_elem(Q, x * ld_x + k, dt), ld_elem(P, y * ld_y + k, dt), phi);
   }
+  // FP8 input: the row scales are powers of two, so scaling the sum is exact
+  if (dt == IPFP_FP8E4M3) phi *= (double)scale_x[x] * (double)scale_y[y];
   mu[i] = exp(phi / (2.0 * sigma)) * a[x] * b[y];
 }
 
 hipError_t launch_mu_pairs(const void* U, const void* Q, const void* V,
-                           const void* P, ipfp_dtype dt, int64_t ld_x,
+                           const void* P, ipfp_dtype dt, const float* scale_x,
+                           const float* scale_y, int64_t ld_x,
                            int64_t ld_y, int64_t N, int64_t M, int64_t d,
                            double sigma, const double* a, const double* b,
                            const int64_t* xs, const int64_t* ys, int64_t count,
                            double* mu, int32_t* bad, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mu_pairs, dim3((unsigned)((count + 255) / 256)), dim3(256),
-                     0, s, U, Q, V, P, dt, ld_x, ld_y, N, M, d, sigma, a, b, xs,
-                     ys, count, mu, bad);
+                     0, s, U, Q, V, P, dt, scale_x, scale_y, ld_x, ld_y, N, M, d, sigma,
+                     a, b, xs, ys, count, mu, bad);
   return hipGetLastError();
 }
 

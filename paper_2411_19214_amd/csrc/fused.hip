@@ -54,7 +54,8 @@ typedef int intx4 __attribute__((ext_vector_type(4)));
 int64_t fused_kpad(int64_t d, ipfp_dtype compute) {
   const int64_t k2 = 2 * d;
   if (compute == IPFP_FP8E4M3) return ((k2 + 63) / 64) * 64;
-  // BF16: multiples of 32 (two 16-wide MFMA k-steps) keep rows 64-byte aligned
+  // BF16 and FP32: multiples of 32 (two 16-wide BF16 MFMA k-steps, four
+  // 8-wide FP32 k-steps) keep rows 64-byte aligned
   return ((k2 + 31) / 32) * 32;
 }
 
@@ -66,6 +67,7 @@ __device__ __forceinline__ float in_as_float(const void* p, int64_t i,
                                              ipfp_dtype dt) {
   if (dt == IPFP_F64) return (float)static_cast<const double*>(p)[i];
   if (dt == IPFP_F32) return static_cast<const float*>(p)[i];
+  if (dt == IPFP_FP8E4M3) return e4m3_val(static_cast<const uint8_t*>(p)[i]);
   return __uint_as_float((uint32_t)static_cast<const uint16_t*>(p)[i] << 16);
 }
 
@@ -96,28 +98,25 @@ __device__ __forceinline__ uint8_t e4m3_rne(float f) {
   return sign | (uint8_t)code;
 }
 
-__device__ __forceinline__ float e4m3_val(uint8_t c) {
-  const int e = (c >> 3) & 0xF, f = c & 7;
-  float v = e == 0 ? ldexpf((float)f, -9) : ldexpf((float)(8 + f), e - 10);
-  return (c & 0x80) ? -v : v;
-}
-
-// One wave per row; every value is first rounded to FP32 and multiplied by
+// One wave per row; every value is first rounded to FP32 (FP8 input: the
+// code's value times the row's power-of-two scale, exact) and multiplied by
 // the prescale p in FP32. BF16: codes of RNE(p x). FP8: power-of-two scale
 // s = 2^e with the smallest e such that amax(p x) <= 448 s, codes
-// e4m3(p x / s).
+// e4m3(p x / s). FP32: the FP32 products p x themselves.
 __global__ void __launch_bounds__(256)
-    k_pack(const void* A, const void* B, ipfp_dtype in_dt, int64_t ld,
+    k_pack(const void* A, const void* B, ipfp_dtype in_dt, const float* in_scale, int64_t ld,
            int64_t rows, int64_t d, ipfp_dtype compute, int64_t kpad, float p,
            void* out, float* scale, Ctl* ctl) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
   const int64_t k2 = 2 * d;
+  const float rs = in_dt == IPFP_FP8E4M3 ? in_scale[row] : 1.f;
+  if (in_dt == IPFP_FP8E4M3 && lane == 0 && !pow2_scale_ok(rs)) atomicOr(&ctl->bad_margin, 1);
   auto val = [&](int64_t k) {
     const float x = k < d ? in_as_float(A, row * ld + k, in_dt)
                           : in_as_float(B, row * ld + k - d, in_dt);
-    return x * p;
+    return (x * rs) * p;
   };
   bool finite = true;
   float amax = 0.f;
@@ -139,6 +138,9 @@ __global__ void __launch_bounds__(256)
     for (int64_t k = lane; k < kpad; k += 64)
       o[k] = k < k2 ? e4m3_rne(ldexpf(val(k), -e)) : 0;
     if (lane == 0) scale[row] = ldexpf(1.f, e);
+  } else if (compute == IPFP_F32) {
+    float* o = static_cast<float*>(out) + row * kpad;
+    for (int64_t k = lane; k < kpad; k += 64) o[k] = k < k2 ? val(k) : 0.f;
   } else {
     uint16_t* o = static_cast<uint16_t*>(out) + row * kpad;
     for (int64_t k = lane; k < kpad; k += 64)
@@ -147,32 +149,49 @@ __global__ void __launch_bounds__(256)
 }
 
 hipError_t launch_pack(const void* A, const void* B, ipfp_dtype in_dt,
-                       int64_t ld, int64_t rows, int64_t d, ipfp_dtype compute,
-                       int64_t kpad, float prescale, void* out, float* scale,
-                       Ctl* ctl, hipStream_t s) {
+                       const float* in_scale, int64_t ld, int64_t rows, int64_t d,
+                       ipfp_dtype compute, int64_t kpad, float prescale, void* out,
+                       float* scale, Ctl* ctl, hipStream_t s) {
   hipLaunchKernelGGL(k_pack, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, A,
-                     B, in_dt, ld, rows, d, compute, kpad, prescale, out, scale, ctl);
+                     B, in_dt, in_scale, ld, rows, d, compute, kpad, prescale, out, scale,
+                     ctl);
   return hipGetLastError();
 }
 
 // ---- the reduction pass ------------------------------------------------------
 
-// Operand traits: bytes per element, bytes a lane feeds one MFMA (SB) and the
-// K extent of one MFMA (KS).
-template <bool FP8>
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Operand kinds of the fused passes.
+enum OpKind { kBF16 = 0, kFP8 = 1, kF32 = 2 };
+
+// Operand traits: bytes per element (ES), bytes a lane reads per k-step (SB),
+// the K extent of one k-step (KS) and the lane's fragment of a k-step. A
+// k-step is one MFMA for BF16 and FP8 and four for FP32 (a lane's 16 bytes
+// are four consecutive K slots, fed one per 32x32x2 MFMA): both operands read
+// the same packed positions in the same order, so any assignment of K slots
+// to lanes and steps sums the same products.
+template <int OK>
 struct Op;
 template <>
-struct Op<false> {  // BF16, v_mfma_f32_32x32x16_bf16
+struct Op<kBF16> {  // BF16, v_mfma_f32_32x32x16_bf16
   static constexpr int ES = 2, SB = 16, KS = 16;
+  typedef bf16x8 Frag;
 };
 template <>
-struct Op<true> {  // FP8 e4m3, v_mfma_scale_f32_32x32x64_f8f6f4
+struct Op<kFP8> {  // FP8 e4m3, v_mfma_scale_f32_32x32x64_f8f6f4
   static constexpr int ES = 1, SB = 32, KS = 64;
+  typedef intx8 Frag;
+};
+template <>
+struct Op<kF32> {  // FP32, four v_mfma_f32_32x32x2_f32 per k-step
+  static constexpr int ES = 4, SB = 16, KS = 8;
+  typedef floatx4 Frag;
 };
 
 // Reduced rows staged per LDS buffer (a multiple of 64): IPFP_TY (a build-time
 // knob) for packed rows up to 256 bytes, half of it for longer rows so that
-// the double buffer stays near 70 KiB of LDS.
+// the double buffer stays near 70 KiB of LDS (FP32 rows of 2d > 128: 130 KiB).
 #ifndef IPFP_TY
 #define IPFP_TY 128
 #endif
@@ -181,10 +200,39 @@ struct Op<true> {  // FP8 e4m3, v_mfma_scale_f32_32x32x64_f8f6f4
 // BF16 rows of 2d >= 192 fit three waves per SIMD when scheduled for it, but
 // an 8-wave workgroup uses only two of them, and the kernel compiled for two
 // (more registers per wave) is 15-60 % faster there (MI355X, N = M = 1e6);
-// elsewhere the default scheduling is as fast or faster.
-constexpr int pass_max_waves(int kp, bool fp8) { return (!fp8 && kp >= 192) ? 2 : 8; }
+// elsewhere the default scheduling is as fast or faster. FP32 passes keep
+// the whole register file (their operand fragments are twice the BF16 ones):
+// one wave per SIMD, four-wave workgroups.
+constexpr int pass_max_waves(int kp, int ok) {
+  return ok == kF32 ? 1 : ((ok == kBF16 && kp >= 192) ? 2 : 8);
+}
+constexpr int pass_min_waves(int ok) { return ok == kF32 ? 1 : 2; }
 
 constexpr int ty_for(int row_bytes) { return row_bytes <= 256 ? IPFP_TY : IPFP_TY / 2; }
+
+// Register budget: two 32-row output tiles per wave while the operand
+// fragments of both fit in 64 VGPRs per lane (one tile for FP32).
+constexpr int xt_for(int kp, int ok) {
+  return ok == kF32 ? 1 : ((ok == kFP8 ? kp <= 128 : (kp <= 128 && kp != 96)) ? 2 : 1);
+}
+
+static int op_kind(ipfp_dtype compute) {
+  return compute == IPFP_FP8E4M3 ? kFP8 : (compute == IPFP_F32 ? kF32 : kBF16);
+}
+
+// Waves per workgroup of a sum or max pass: 8 when the requested height
+// covers them, else 4; FP32 passes always use 4 (one wave per SIMD).
+static int pass_waves(int ok, int xt, int tile_rows) {
+  return ok != kF32 && tile_rows >= xt * 256 ? 8 : 4;
+}
+
+static int elem_bytes(int ok) { return ok == kFP8 ? 1 : (ok == kF32 ? 4 : 2); }
+
+// The kpads every operand kind is built for (BF16 and FP32 rows are padded to
+// multiples of 32 values, FP8 rows to multiples of 64).
+#define IPFP_KP16(X, OKV) X(32, OKV) X(64, OKV) X(96, OKV) X(128, OKV) X(160, OKV) \
+  X(192, OKV) X(224, OKV) X(256, OKV)
+#define IPFP_KP8(X, OKV) X(64, OKV) X(128, OKV) X(192, OKV) X(256, OKV)
 
 // Binary exponent e with w = m 2^e, m in [0.5, 1) (INT_MIN for w = 0).
 __device__ __forceinline__ int exponent_of(double w) {
@@ -194,30 +242,29 @@ __device__ __forceinline__ int exponent_of(double w) {
   return e;
 }
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
 // Everything a reduction pass keeps per wave, plus the staging of the reduced
 // side through LDS; shared by the max pass and the sum pass.
-template <int KP, int XT, int WAVES, bool FP8>
+template <int KP, int XT, int WAVES, int OK>
 struct PassCore {
-  typedef Op<FP8> O;
+  typedef Op<OK> O;
   static constexpr int RB = KP * O::ES;           // bytes per packed row
   static constexpr int kTY = ty_for(RB);          // reduced rows per stage
-  static constexpr int NS = KP / O::KS;           // MFMAs per 32x32 tile
+  static constexpr int NS = KP / O::KS;           // k-steps per 32x32 tile
   static constexpr int LS = RB + 16;              // LDS row stride (pad)
   static constexpr int NT = WAVES * 64;
   static constexpr int CH = kTY * RB / 16;        // 16-byte chunks per stage
   static constexpr int CPT = (CH + NT - 1) / NT;  // chunks per thread
   static constexpr int SUB = kTY / 32;
-  typedef typename std::conditional<FP8, intx8, bf16x8>::type Frag;
+  typedef typename O::Frag Frag;
 };
 
-// Reads the A fragment of k-step s for reduced row `row` of a staged tile.
-template <bool FP8, typename Frag>
-__device__ __forceinline__ Frag lds_frag(const uint8_t* arow, int s) {
-  typedef Op<FP8> O;
-  Frag f;
-  if constexpr (FP8) {
+// Reads the fragment of k-step s for the packed row at `arow` (which already
+// points at the lane's half: + h * SB).
+template <int OK>
+__device__ __forceinline__ typename Op<OK>::Frag lds_frag(const uint8_t* arow, int s) {
+  typedef Op<OK> O;
+  typename O::Frag f;
+  if constexpr (OK == kFP8) {
     intx4 lo = *reinterpret_cast<const intx4*>(arow + s * 2 * O::SB);
     intx4 hi = *reinterpret_cast<const intx4*>(arow + s * 2 * O::SB + 16);
     intx8 v;
@@ -230,15 +277,42 @@ __device__ __forceinline__ Frag lds_frag(const uint8_t* arow, int s) {
   return f;
 }
 
-template <bool FP8, typename Frag>
-__device__ __forceinline__ floatx16 mfma_step(const Frag& a, const Frag& b, floatx16 c,
+template <int OK>
+__device__ __forceinline__ floatx16 mfma_step(const typename Op<OK>::Frag& a,
+                                              const typename Op<OK>::Frag& b, floatx16 c,
                                               int asc, int bsc) {
-  if constexpr (FP8)
+  if constexpr (OK == kFP8) {
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
         *reinterpret_cast<const intx8*>(&a), *reinterpret_cast<const intx8*>(&b), c, 0, 0,
         0, asc, 0, bsc);
-  else
+  } else if constexpr (OK == kF32) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j], b[j], c, 0, 0, 0);
+    return c;
+  } else {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+}
+
+// Two independent accumulator chains advanced by one k-step each. For FP32
+// the chains' four MFMAs alternate, so no MFMA waits on the one before it.
+template <int OK>
+__device__ __forceinline__ void mfma_pair(const typename Op<OK>::Frag& a0,
+                                          const typename Op<OK>::Frag& b0, floatx16& c0,
+                                          int asc0, int bsc0,
+                                          const typename Op<OK>::Frag& a1,
+                                          const typename Op<OK>::Frag& b1, floatx16& c1,
+                                          int asc1, int bsc1) {
+  if constexpr (OK == kF32) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[j], b0[j], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[j], b1[j], c1, 0, 0, 0);
+    }
+  } else {
+    c0 = mfma_step<OK>(a0, b0, c0, asc0, bsc0);
+    c1 = mfma_step<OK>(a1, b1, c1, asc1, bsc1);
+  }
 }
 
 // Work item of block `bid` in a list of W items ordered split-major (all row
@@ -267,16 +341,17 @@ __device__ __forceinline__ int xcd_item(int bid, int W) {
 // `bid` is the workgroup's index within this market's grid (blockIdx.x for a
 // single-market launch, the offset within the market's range of a grouped
 // launch).
-template <int KP, int XT, int WAVES, bool FP8, bool MAXMODE>
+template <int KP, int XT, int WAVES, int OK, bool MAXMODE>
 __device__ __forceinline__ void fused_pass_body(
     const uint8_t* __restrict__ Xo, const float* __restrict__ xscale,
     const uint8_t* __restrict__ Yr, const float* __restrict__ yscale,
     const double* __restrict__ wred, int red_dbuf, int exp_red, int exp_out,
     const float* __restrict__ shift, int R, int L, int tiles_per_split, int nsplit,
     double* __restrict__ part, Ctl* ctl, const int bid) {
-  typedef PassCore<KP, XT, WAVES, FP8> C;
+  typedef PassCore<KP, XT, WAVES, OK> C;
   typedef typename C::Frag Frag;
-  typedef Op<FP8> O;
+  typedef Op<OK> O;
+  constexpr bool FP8 = OK == kFP8;
   constexpr int RB = C::RB, kTY = C::kTY, NS = C::NS, LS = C::LS, NT = C::NT;
   constexpr int CH = C::CH, CPT = C::CPT, SUB = C::SUB;
 
@@ -322,7 +397,7 @@ __device__ __forceinline__ void fused_pass_body(
     const uint8_t* src = Xo + (int64_t)(ok ? x : 0) * RB + h * O::SB;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      Frag f = lds_frag<FP8, Frag>(src, s);   // same layout as a staged row
+      Frag f = lds_frag<OK>(src, s);   // same layout as a staged row
       if (!ok) *reinterpret_cast<intx4*>(&f) = intx4{0, 0, 0, 0};
       if constexpr (FP8) {
         if (!ok) reinterpret_cast<intx4*>(&f)[1] = intx4{0, 0, 0, 0};
@@ -384,12 +459,12 @@ __device__ __forceinline__ void fused_pass_body(
   // and their running-sum slots; a zero-weight dummy before the first tile
   constexpr int NPAIR = XT == 2 ? SUB : SUB / 2;
   // the paired, pipelined schedule pays off where the MFMAs dominate a step
-  // (FP8 operands, BF16 with 2d = 128 or 2d >= 192); elsewhere one chain at
-  // a time
-  constexpr bool kPaired = FP8 || KP == 128 || KP >= 192;
+  // (FP8 and FP32 operands, BF16 with 2d = 128 or 2d >= 192); elsewhere one
+  // chain at a time
+  constexpr bool kPaired = OK != kBF16 || KP == 128 || KP >= 192;
   // BF16 with 2d = 128: explicit scheduling groups (below) interleave each
   // MFMA with its share of the pending epilogue
-  constexpr bool kGrouped = !FP8 && KP == 128;
+  constexpr bool kGrouped = OK == kBF16 && KP == 128;
   floatx16 pc0, pc1;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -446,10 +521,10 @@ __device__ __forceinline__ void fused_pass_body(
         for (int t = 0; t < XT; ++t) acc[t] = shv[t];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          const Frag f = lds_frag<FP8, Frag>(arow, s);
+          const Frag f = lds_frag<OK>(arow, s);
 #pragma unroll
           for (int t = 0; t < XT; ++t)
-            acc[t] = mfma_step<FP8>(f, bfrag[t][s], acc[t], asc, xsc[t]);
+            acc[t] = mfma_step<OK>(f, bfrag[t][s], acc[t], asc, xsc[t]);
         }
 #pragma unroll
         for (int t = 0; t < XT; ++t) {
@@ -475,7 +550,7 @@ __device__ __forceinline__ void fused_pass_body(
           floatx16 acc = shv[t];
 #pragma unroll
           for (int s = 0; s < NS; ++s)
-            acc = mfma_step<FP8>(lds_frag<FP8, Frag>(arow, s), bfrag[t][s], acc, asc, xsc[t]);
+            acc = mfma_step<OK>(lds_frag<OK>(arow, s), bfrag[t][s], acc, asc, xsc[t]);
           float s0 = __builtin_amdgcn_exp2f(acc[0]) * w[0];
           float s1 = __builtin_amdgcn_exp2f(acc[1]) * w[1];
 #pragma unroll
@@ -507,10 +582,10 @@ __device__ __forceinline__ void fused_pass_body(
         floatx16 a0 = shv[ta], a1 = shv[tb];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          const Frag f0 = lds_frag<FP8, Frag>(arow0, s);
-          const Frag f1 = XT == 2 ? f0 : lds_frag<FP8, Frag>(arow1, s);
-          a0 = mfma_step<FP8>(f0, bfrag[ta][s], a0, asc0, xsc[ta]);
-          a1 = mfma_step<FP8>(f1, bfrag[tb][s], a1, asc1, xsc[tb]);
+          const Frag f0 = lds_frag<OK>(arow0, s);
+          const Frag f1 = XT == 2 ? f0 : lds_frag<OK>(arow1, s);
+          mfma_pair<OK>(f0, bfrag[ta][s], a0, asc0, xsc[ta], f1, bfrag[tb][s], a1, asc1,
+                        xsc[tb]);
 #pragma unroll
           for (int u = 0; u < PER; ++u)
             if (s * PER + u < 16) epi1(s * PER + u, w0, w1, s4);
@@ -570,16 +645,16 @@ __device__ __forceinline__ void fused_pass_body(
   }
 }
 
-template <int KP, int XT, int WAVES, bool FP8, bool MAXMODE>
+template <int KP, int XT, int WAVES, int OK, bool MAXMODE>
 __global__ void __launch_bounds__(WAVES * 64)
-    __attribute__((amdgpu_waves_per_eu(2, pass_max_waves(KP, FP8))))
+    __attribute__((amdgpu_waves_per_eu(pass_min_waves(OK), pass_max_waves(KP, OK))))
     k_fused_pass(const uint8_t* __restrict__ Xo, const float* __restrict__ xscale,
                  const uint8_t* __restrict__ Yr, const float* __restrict__ yscale,
                  const double* __restrict__ wred, int red_dbuf, int exp_red,
                  int exp_out, const float* __restrict__ shift, int R, int L,
                  int tiles_per_split, int nsplit, double* __restrict__ part,
                  Ctl* ctl) {
-  fused_pass_body<KP, XT, WAVES, FP8, MAXMODE>(Xo, xscale, Yr, yscale, wred, red_dbuf,
+  fused_pass_body<KP, XT, WAVES, OK, MAXMODE>(Xo, xscale, Yr, yscale, wred, red_dbuf,
                                                exp_red, exp_out, shift, R, L,
                                                tiles_per_split, nsplit, part, ctl,
                                                (int)blockIdx.x);
@@ -598,14 +673,14 @@ __device__ __forceinline__ int group_find(const int32_t* __restrict__ first, int
   return lo;
 }
 
-template <int KP, int XT, int WAVES, bool FP8>
+template <int KP, int XT, int WAVES, int OK>
 __global__ void __launch_bounds__(WAVES * 64)
-    __attribute__((amdgpu_waves_per_eu(2, pass_max_waves(KP, FP8))))
+    __attribute__((amdgpu_waves_per_eu(pass_min_waves(OK), pass_max_waves(KP, OK))))
     k_group_pass(const GroupHalf* __restrict__ g, const int32_t* __restrict__ idx,
                  const int32_t* __restrict__ first, int count) {
   const int j = group_find(first, count, (int)blockIdx.x);
   const GroupHalf& p = g[__builtin_amdgcn_readfirstlane(idx[j])];
-  fused_pass_body<KP, XT, WAVES, FP8, false>(
+  fused_pass_body<KP, XT, WAVES, OK, false>(
       p.Xo, p.xscale, p.Yr, p.yscale, p.wred, p.red_dbuf, p.exp_red, p.exp_out, p.shift,
       p.R, p.L, p.tiles_per_split, p.nsplit, p.part, p.ctl,
       (int)blockIdx.x - __builtin_amdgcn_readfirstlane(first[j]));
@@ -637,16 +712,17 @@ __device__ __forceinline__ void topk_insert(float (&ts)[KT], int (&ti)[KT], floa
   }
 }
 
-template <int KP, bool FP8, int KT>
+template <int KP, int OK, int KT>
 __global__ void __launch_bounds__(256)
     k_topk_pass(const uint8_t* __restrict__ Xo, const float* __restrict__ xscale,
                 const uint8_t* __restrict__ Yr, const float* __restrict__ yscale,
                 const double* __restrict__ wred, int R, int L, int tiles_per_split,
                 int nsplit, float* __restrict__ pscore, int32_t* __restrict__ pidx) {
   constexpr int WAVES = 4;
-  typedef PassCore<KP, 1, WAVES, FP8> C;
+  typedef PassCore<KP, 1, WAVES, OK> C;
   typedef typename C::Frag Frag;
-  typedef Op<FP8> O;
+  typedef Op<OK> O;
+  constexpr bool FP8 = OK == kFP8;
   constexpr int RB = C::RB, kTY = C::kTY, NS = C::NS, LS = C::LS, NT = C::NT;
   constexpr int CH = C::CH, CPT = C::CPT, SUB = C::SUB;
   __shared__ __attribute__((aligned(16))) uint8_t ys[2][kTY * LS];
@@ -668,7 +744,7 @@ __global__ void __launch_bounds__(256)
     const uint8_t* src = Xo + (int64_t)(ok ? x : 0) * RB + h * O::SB;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      Frag f = lds_frag<FP8, Frag>(src, s);
+      Frag f = lds_frag<OK>(src, s);
       if (!ok) *reinterpret_cast<intx4*>(&f) = intx4{0, 0, 0, 0};
       if constexpr (FP8) {
         if (!ok) reinterpret_cast<intx4*>(&f)[1] = intx4{0, 0, 0, 0};
@@ -729,7 +805,7 @@ __global__ void __launch_bounds__(256)
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      acc = mfma_step<FP8>(lds_frag<FP8, Frag>(arow, s), bfrag[s], acc, asc, xsc);
+      acc = mfma_step<OK>(lds_frag<OK>(arow, s), bfrag[s], acc, asc, xsc);
     return acc;
   };
   for (int tile = t0; tile < t1; ++tile) {
@@ -814,15 +890,15 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <int KP, bool FP8, int KT>
+template <int KP, int OK, int KT>
 static hipError_t topk_t(const FusedPass& fp, const double* a_out, int k, int splits,
                          float* pscore, int32_t* pidx, int32_t* idx_out, float* score_out,
                          hipStream_t s) {
-  constexpr int kTY = ty_for(KP * Op<FP8>::ES);
+  constexpr int kTY = ty_for(KP * Op<OK>::ES);
   const int64_t rblocks = (fp.out.rows + 127) / 128;
   const int T = (int)((fp.red.rows + kTY - 1) / kTY);
   const int tps = (T + splits - 1) / splits;
-  hipLaunchKernelGGL((k_topk_pass<KP, FP8, KT>), dim3((unsigned)(rblocks * splits)),
+  hipLaunchKernelGGL((k_topk_pass<KP, OK, KT>), dim3((unsigned)(rblocks * splits)),
                      dim3(256), 0, s, (const uint8_t*)fp.out.ops, fp.out.scale,
                      (const uint8_t*)fp.red.ops, fp.red.scale, fp.w_red, (int)fp.out.rows,
                      (int)fp.red.rows, tps, splits, pscore, pidx);
@@ -834,18 +910,18 @@ static hipError_t topk_t(const FusedPass& fp, const double* a_out, int k, int sp
   return hipGetLastError();
 }
 
-template <int KP, bool FP8>
+template <int KP, int OK>
 static hipError_t topk_kp(const FusedPass& fp, const double* a_out, int k, int splits,
                           float* pscore, int32_t* pidx, int32_t* idx_out, float* score_out,
                           hipStream_t s) {
   const int kt = topk_width(k);
   if (kt == 8)
-    return topk_t<KP, FP8, 8>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
+    return topk_t<KP, OK, 8>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
   if (kt == 12)
-    return topk_t<KP, FP8, 12>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
+    return topk_t<KP, OK, 12>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
   if (kt == 16)
-    return topk_t<KP, FP8, 16>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
-  return topk_t<KP, FP8, 32>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
+    return topk_t<KP, OK, 16>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
+  return topk_t<KP, OK, 32>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
 }
 
 int topk_width(int k) { return k <= 8 ? 8 : (k <= 12 ? 12 : (k <= 16 ? 16 : 32)); }
@@ -856,28 +932,25 @@ hipError_t launch_topk(const FusedPass& fp, const double* a_out, int k, int spli
                        float* pscore, int32_t* pidx, int32_t* idx_out, float* score_out,
                        hipStream_t s) {
   if (k < 1 || k > 32) return hipErrorInvalidValue;
-#define IPFP_TOPK_CASE(KPV, F8)                                                       \
+#define IPFP_TOPK_CASE(KPV, OKV)                                                      \
   case KPV:                                                                           \
-    return topk_kp<KPV, F8>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
-  if (fp.compute == IPFP_FP8E4M3) {
-    switch (fp.kpad) {
-      IPFP_TOPK_CASE(64, true)
-      IPFP_TOPK_CASE(128, true)
-      IPFP_TOPK_CASE(192, true)
-      IPFP_TOPK_CASE(256, true)
-      default: return hipErrorInvalidValue;
-    }
-  }
-  switch (fp.kpad) {
-    IPFP_TOPK_CASE(32, false)
-    IPFP_TOPK_CASE(64, false)
-    IPFP_TOPK_CASE(96, false)
-    IPFP_TOPK_CASE(128, false)
-    IPFP_TOPK_CASE(160, false)
-    IPFP_TOPK_CASE(192, false)
-    IPFP_TOPK_CASE(224, false)
-    IPFP_TOPK_CASE(256, false)
-    default: return hipErrorInvalidValue;
+    return topk_kp<KPV, OKV>(fp, a_out, k, splits, pscore, pidx, idx_out, score_out, s);
+  switch (op_kind(fp.compute)) {
+    case kFP8:
+      switch (fp.kpad) {
+        IPFP_KP8(IPFP_TOPK_CASE, kFP8)
+        default: return hipErrorInvalidValue;
+      }
+    case kF32:
+      switch (fp.kpad) {
+        IPFP_KP16(IPFP_TOPK_CASE, kF32)
+        default: return hipErrorInvalidValue;
+      }
+    default:
+      switch (fp.kpad) {
+        IPFP_KP16(IPFP_TOPK_CASE, kBF16)
+        default: return hipErrorInvalidValue;
+      }
   }
 #undef IPFP_TOPK_CASE
 }
@@ -941,9 +1014,9 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
                 const int* __restrict__ Eptr, const float* __restrict__ shift, int R, int L,
                 int tiles_per_split, int nsplit, int ngroups, double* __restrict__ gpart) {
   constexpr int WAVES = kGradWaves;
-  typedef PassCore<KP, 1, WAVES, false> C;
+  typedef PassCore<KP, 1, WAVES, kBF16> C;
   typedef typename C::Frag Frag;
-  typedef Op<false> O;
+  typedef Op<kBF16> O;
   constexpr int RB = C::RB, kTY = C::kTY, NS = C::NS, LS = C::LS, NT = C::NT;
   constexpr int CH = C::CH, CPT = C::CPT, SUB = C::SUB;
   constexpr int NB = KP / 32;               // 32-column blocks of the value rows
@@ -975,7 +1048,7 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
     const uint8_t* src = Xo + (int64_t)(ok ? x : 0) * RB + h * O::SB;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      Frag f = lds_frag<false, Frag>(src, s);
+      Frag f = lds_frag<kBF16>(src, s);
       if (!ok) *reinterpret_cast<intx4*>(&f) = intx4{0, 0, 0, 0};
       bfrag[s] = f;
     }
@@ -1043,7 +1116,7 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
     for (int j = 0; j < 16; ++j) acc[j] = hv;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      acc = mfma_step<false>(lds_frag<false, Frag>(arow, s), bfrag[s], acc, 127, 127);
+      acc = mfma_step<kBF16>(lds_frag<kBF16>(arow, s), bfrag[s], acc, 127, 127);
     return acc;
   };
   for (int tile = t0; tile < t1; ++tile) {
@@ -1301,12 +1374,16 @@ __global__ void k_shift_from_max(const double* part, int splits, int64_t R,
 // over the reduced side with FP32 dot products of the same packed operands
 // and FP64 log2 weights, the first for the maximum exponent, the second for
 // the sum.
-template <bool FP8>
+template <int OK>
 __device__ __forceinline__ float dot_packed(const uint8_t* a, const uint8_t* b,
                                             int kpad) {
   float acc = 0.f;
-  if (FP8) {
+  if constexpr (OK == kFP8) {
     for (int k = 0; k < kpad; ++k) acc = fmaf(e4m3_val(a[k]), e4m3_val(b[k]), acc);
+  } else if constexpr (OK == kF32) {
+    const float* a32 = reinterpret_cast<const float*>(a);
+    const float* b32 = reinterpret_cast<const float*>(b);
+    for (int k = 0; k < kpad; ++k) acc = fmaf(a32[k], b32[k], acc);
   } else {
     const uint16_t* a16 = reinterpret_cast<const uint16_t*>(a);
     const uint16_t* b16 = reinterpret_cast<const uint16_t*>(b);
@@ -1317,7 +1394,7 @@ __device__ __forceinline__ float dot_packed(const uint8_t* a, const uint8_t* b,
   return acc;
 }
 
-template <bool FP8>
+template <int OK>
 __device__ __forceinline__ void fixup_body(
     const uint8_t* Xo, const float* xscale, const uint8_t* Yr, const float* yscale, int kpad,
     const double* wred, int red_dbuf, int exp_out, int64_t L, int64_t R, const double* marg,
@@ -1331,7 +1408,8 @@ __device__ __forceinline__ void fixup_body(
   const double* w_old = dbuf ? w2 + (int64_t)(i & 1) * R : w2;
   double* w_new = dbuf ? w2 + (int64_t)((i + 1) & 1) * R : w2;
   if (red_dbuf) wred += (int64_t)(i & 1) * L;
-  const int ES = FP8 ? 1 : 2;
+  constexpr bool FP8 = OK == kFP8;
+  constexpr int ES = Op<OK>::ES;
   double res = 0.0;
   int ex = INT_MIN;
   for (int k = bid; k < count; k += nblocks) {
@@ -1341,7 +1419,7 @@ __device__ __forceinline__ void fixup_body(
     double tmax = -INFINITY;
     for (int64_t y = threadIdx.x; y < L; y += 256) {
       const float sc = FP8 ? sx * yscale[y] : 1.f;
-      const double t = (double)(dot_packed<FP8>(xr, Yr + y * kpad * ES, kpad) * sc) +
+      const double t = (double)(dot_packed<OK>(xr, Yr + y * kpad * ES, kpad) * sc) +
                        log2(wred[y]);
       tmax = fmax(tmax, t);
     }
@@ -1354,7 +1432,7 @@ __device__ __forceinline__ void fixup_body(
     if (tmax > -INFINITY) {
       for (int64_t y = threadIdx.x; y < L; y += 256) {
         const float sc = FP8 ? sx * yscale[y] : 1.f;
-        const double t = (double)(dot_packed<FP8>(xr, Yr + y * kpad * ES, kpad) * sc) +
+        const double t = (double)(dot_packed<OK>(xr, Yr + y * kpad * ES, kpad) * sc) +
                          log2(wred[y]);
         sum += exp2(t - tmax);
       }
@@ -1373,25 +1451,25 @@ __device__ __forceinline__ void fixup_body(
   block_finish(res, ex, &res_slot[bid], &ctl->wexp[exp_out]);
 }
 
-template <bool FP8>
+template <int OK>
 __global__ void __launch_bounds__(256)
     k_fused_fixup(const uint8_t* Xo, const float* xscale, const uint8_t* Yr,
                   const float* yscale, int kpad, const double* wred, int red_dbuf,
                   int exp_out, int64_t L, int64_t R, const double* marg, double* w2, int dbuf,
                   double* res_slot, const int32_t* fix_list, int residual,
                   Ctl* ctl) {
-  fixup_body<FP8>(Xo, xscale, Yr, yscale, kpad, wred, red_dbuf, exp_out, L, R, marg, w2,
+  fixup_body<OK>(Xo, xscale, Yr, yscale, kpad, wred, red_dbuf, exp_out, L, R, marg, w2,
                   dbuf, res_slot, fix_list, residual, ctl, (int)blockIdx.x,
                   (int)gridDim.x);
 }
 
 // Grouped fixup: `per` blocks per market, market j owns blocks [j per, (j+1) per).
-template <bool FP8>
+template <int OK>
 __global__ void __launch_bounds__(256)
     k_group_fixup(const GroupHalf* __restrict__ g, int per) {
   const int j = (int)blockIdx.x / per;
   const GroupHalf& p = g[j];
-  fixup_body<FP8>(p.Xo, p.xscale, p.Yr, p.yscale, p.kpad, p.wred, p.red_dbuf, p.exp_out,
+  fixup_body<OK>(p.Xo, p.xscale, p.Yr, p.yscale, p.kpad, p.wred, p.red_dbuf, p.exp_out,
                   p.L, p.R, p.marg, p.w2, p.dbuf, p.res_slot, p.fix_list, p.residual, p.ctl,
                   (int)blockIdx.x - j * per, per);
 }
@@ -1416,15 +1494,15 @@ hipError_t launch_init_exp(const double* w, int64_t len, Ctl* ctl, int idx,
 
 // ---- dispatch ---------------------------------------------------------------
 
-template <int KP, int XT, int WAVES, bool FP8, bool MAXMODE>
+template <int KP, int XT, int WAVES, int OK, bool MAXMODE>
 static hipError_t pass_t(const FusedPass& fp, Ctl* ctl, hipStream_t s) {
-  constexpr int kTY = ty_for(KP * Op<FP8>::ES);
+  constexpr int kTY = ty_for(KP * Op<OK>::ES);
   const int rows_per_wg = WAVES * XT * 32;
   const int64_t rblocks = (fp.out.rows + rows_per_wg - 1) / rows_per_wg;
   const int T = (int)((fp.red.rows + kTY - 1) / kTY);
   const int tps = (T + fp.splits - 1) / fp.splits;
   const int64_t grid = rblocks * fp.splits;
-  hipLaunchKernelGGL((k_fused_pass<KP, XT, WAVES, FP8, MAXMODE>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((k_fused_pass<KP, XT, WAVES, OK, MAXMODE>), dim3((unsigned)grid),
                      dim3(WAVES * 64), 0, s, (const uint8_t*)fp.out.ops,
                      fp.out.scale, (const uint8_t*)fp.red.ops, fp.red.scale,
                      fp.w_red, fp.red_dbuf, fp.exp_red, fp.exp_out, fp.shift, (int)fp.out.rows,
@@ -1432,39 +1510,39 @@ static hipError_t pass_t(const FusedPass& fp, Ctl* ctl, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Register budget: two 32-row output tiles per wave while the operand
-// fragments of both fit in 64 VGPRs per lane.
-constexpr int xt_for(int kp, bool fp8) { return (fp8 ? kp <= 128 : (kp <= 128 && kp != 96)) ? 2 : 1; }
-
-template <int KP, bool FP8, bool MAXMODE>
+template <int KP, int OK, bool MAXMODE>
 static hipError_t pass_kp(const FusedPass& fp, Ctl* ctl, hipStream_t s) {
-  constexpr int XT = xt_for(KP, FP8);
-  if (fp.tile_rows >= XT * 256) return pass_t<KP, XT, 8, FP8, MAXMODE>(fp, ctl, s);
-  return pass_t<KP, XT, 4, FP8, MAXMODE>(fp, ctl, s);
+  constexpr int XT = xt_for(KP, OK);
+  if constexpr (OK == kF32) {
+    return pass_t<KP, XT, 4, OK, MAXMODE>(fp, ctl, s);
+  } else {
+    if (pass_waves(OK, XT, fp.tile_rows) == 8) return pass_t<KP, XT, 8, OK, MAXMODE>(fp, ctl, s);
+    return pass_t<KP, XT, 4, OK, MAXMODE>(fp, ctl, s);
+  }
 }
 
 template <bool MAXMODE>
 static hipError_t pass_any(const FusedPass& fp, Ctl* ctl, hipStream_t s) {
-  if (fp.compute == IPFP_FP8E4M3) {
-    switch (fp.kpad) {
-      case 64: return pass_kp<64, true, MAXMODE>(fp, ctl, s);
-      case 128: return pass_kp<128, true, MAXMODE>(fp, ctl, s);
-      case 192: return pass_kp<192, true, MAXMODE>(fp, ctl, s);
-      case 256: return pass_kp<256, true, MAXMODE>(fp, ctl, s);
-      default: return hipErrorInvalidValue;
-    }
+#define IPFP_PASS_CASE(K, OKV) \
+  case K: return pass_kp<K, OKV, MAXMODE>(fp, ctl, s);
+  switch (op_kind(fp.compute)) {
+    case kFP8:
+      switch (fp.kpad) {
+        IPFP_KP8(IPFP_PASS_CASE, kFP8)
+        default: return hipErrorInvalidValue;
+      }
+    case kF32:
+      switch (fp.kpad) {
+        IPFP_KP16(IPFP_PASS_CASE, kF32)
+        default: return hipErrorInvalidValue;
+      }
+    default:
+      switch (fp.kpad) {
+        IPFP_KP16(IPFP_PASS_CASE, kBF16)
+        default: return hipErrorInvalidValue;
+      }
   }
-  switch (fp.kpad) {
-    case 32: return pass_kp<32, false, MAXMODE>(fp, ctl, s);
-    case 64: return pass_kp<64, false, MAXMODE>(fp, ctl, s);
-    case 96: return pass_kp<96, false, MAXMODE>(fp, ctl, s);
-    case 128: return pass_kp<128, false, MAXMODE>(fp, ctl, s);
-    case 160: return pass_kp<160, false, MAXMODE>(fp, ctl, s);
-    case 192: return pass_kp<192, false, MAXMODE>(fp, ctl, s);
-    case 224: return pass_kp<224, false, MAXMODE>(fp, ctl, s);
-    case 256: return pass_kp<256, false, MAXMODE>(fp, ctl, s);
-    default: return hipErrorInvalidValue;
-  }
+#undef IPFP_PASS_CASE
 }
 
 hipError_t launch_fused_pass(const FusedPass& fp, Ctl* ctl, hipStream_t s) {
@@ -1486,16 +1564,16 @@ hipError_t launch_fused_shift(const FusedPass& fp, Ctl* ctl, hipStream_t s) {
 // ones; BF16 with 2d = 128 is 1-2 % faster with 8 waves; one-tile kernels use
 // 8 waves either way.
 int fused_default_tile_rows(int64_t kpad, ipfp_dtype compute) {
+  if (compute == IPFP_F32) return 128;
   const bool fp8 = compute == IPFP_FP8E4M3;
   if (fp8 ? kpad <= 128 : kpad == 64) return 256;
   return 512;
 }
 
 int fused_rows_per_wg(int64_t kpad, ipfp_dtype compute, int tile_rows) {
-  const bool fp8 = compute == IPFP_FP8E4M3;
-  const int xt = xt_for((int)kpad, fp8);
-  const int waves = tile_rows >= xt * 256 ? 8 : 4;
-  return waves * xt * 32;
+  const int ok = op_kind(compute);
+  const int xt = xt_for((int)kpad, ok);
+  return pass_waves(ok, xt, tile_rows) * xt * 32;
 }
 
 hipError_t launch_fused_combine(const FusedPass& fp, double* w2, int dbuf,
@@ -1514,43 +1592,41 @@ int fused_fixup_blocks() { return kFixupBlocks; }
 
 hipError_t launch_fused_fixup(const FusedPass& fp, double* w2, int dbuf,
                               double* res_slot, Ctl* ctl, hipStream_t s) {
-  if (fp.compute == IPFP_FP8E4M3)
-    hipLaunchKernelGGL(k_fused_fixup<true>, dim3(kFixupBlocks), dim3(256), 0, s,
-                       (const uint8_t*)fp.out.ops, fp.out.scale,
-                       (const uint8_t*)fp.red.ops, fp.red.scale, (int)fp.kpad,
-                       fp.w_red, fp.red_dbuf, fp.exp_out, fp.red.rows, fp.out.rows, fp.marg, w2,
-                       dbuf, res_slot, fp.fix_list, fp.residual ? 1 : 0, ctl);
-  else
-    hipLaunchKernelGGL(k_fused_fixup<false>, dim3(kFixupBlocks), dim3(256), 0, s,
-                       (const uint8_t*)fp.out.ops, fp.out.scale,
-                       (const uint8_t*)fp.red.ops, fp.red.scale, (int)fp.kpad,
-                       fp.w_red, fp.red_dbuf, fp.exp_out, fp.red.rows, fp.out.rows, fp.marg, w2,
-                       dbuf, res_slot, fp.fix_list, fp.residual ? 1 : 0, ctl);
+#define IPFP_FIXUP_ARGS                                                                     \
+  dim3(kFixupBlocks), dim3(256), 0, s, (const uint8_t*)fp.out.ops, fp.out.scale,           \
+      (const uint8_t*)fp.red.ops, fp.red.scale, (int)fp.kpad, fp.w_red, fp.red_dbuf,        \
+      fp.exp_out, fp.red.rows, fp.out.rows, fp.marg, w2, dbuf, res_slot, fp.fix_list,      \
+      fp.residual ? 1 : 0, ctl
+  switch (op_kind(fp.compute)) {
+    case kFP8: hipLaunchKernelGGL(k_fused_fixup<kFP8>, IPFP_FIXUP_ARGS); break;
+    case kF32: hipLaunchKernelGGL(k_fused_fixup<kF32>, IPFP_FIXUP_ARGS); break;
+    default: hipLaunchKernelGGL(k_fused_fixup<kBF16>, IPFP_FIXUP_ARGS); break;
+  }
+#undef IPFP_FIXUP_ARGS
   return hipGetLastError();
 }
 
 // ---- grouped dispatch -----------------------------------------------------------
 
 void fused_pass_grid(const FusedPass& fp, int64_t* blocks, int* tiles_per_split) {
-  const bool fp8 = fp.compute == IPFP_FP8E4M3;
   const int rows_per_wg = fused_rows_per_wg(fp.kpad, fp.compute, fp.tile_rows);
-  const int ty = ty_for((int)fp.kpad * (fp8 ? 1 : 2));
+  const int ty = ty_for((int)fp.kpad * elem_bytes(op_kind(fp.compute)));
   const int64_t rblocks = (fp.out.rows + rows_per_wg - 1) / rows_per_wg;
   const int T = (int)((fp.red.rows + ty - 1) / ty);
   *tiles_per_split = (T + fp.splits - 1) / fp.splits;
   *blocks = rblocks * fp.splits;
 }
 
-template <int KP, bool FP8>
+template <int KP, int OK>
 static hipError_t group_pass_kp(const GroupHalf* g, const int32_t* idx,
                                 const int32_t* first, int count, int total, int tile_rows,
                                 hipStream_t s) {
-  constexpr int XT = xt_for(KP, FP8);
-  if (tile_rows >= XT * 256)
-    hipLaunchKernelGGL((k_group_pass<KP, XT, 8, FP8>), dim3((unsigned)total), dim3(8 * 64),
+  constexpr int XT = xt_for(KP, OK);
+  if (pass_waves(OK, XT, tile_rows) == 8)
+    hipLaunchKernelGGL((k_group_pass<KP, XT, 8, OK>), dim3((unsigned)total), dim3(8 * 64),
                        0, s, g, idx, first, count);
   else
-    hipLaunchKernelGGL((k_group_pass<KP, XT, 4, FP8>), dim3((unsigned)total), dim3(4 * 64),
+    hipLaunchKernelGGL((k_group_pass<KP, XT, 4, OK>), dim3((unsigned)total), dim3(4 * 64),
                        0, s, g, idx, first, count);
   return hipGetLastError();
 }
@@ -1559,26 +1635,22 @@ hipError_t launch_group_pass(const GroupHalf* g, const int32_t* idx, const int32
                              int count, int total, int64_t kpad, ipfp_dtype compute,
                              int tile_rows, hipStream_t s) {
   if (count <= 0 || total <= 0) return hipSuccess;
-  if (compute == IPFP_FP8E4M3) {
-    switch (kpad) {
-      case 64: return group_pass_kp<64, true>(g, idx, first, count, total, tile_rows, s);
-      case 128: return group_pass_kp<128, true>(g, idx, first, count, total, tile_rows, s);
-      case 192: return group_pass_kp<192, true>(g, idx, first, count, total, tile_rows, s);
-      case 256: return group_pass_kp<256, true>(g, idx, first, count, total, tile_rows, s);
-      default: return hipErrorInvalidValue;
-    }
+#define IPFP_GROUP_CASE(K, OKV) \
+  case K: return group_pass_kp<K, OKV>(g, idx, first, count, total, tile_rows, s);
+  switch (op_kind(compute)) {
+    case kFP8:
+      switch (kpad) {
+        IPFP_KP8(IPFP_GROUP_CASE, kFP8)
+        default: return hipErrorInvalidValue;
+      }
+    case kBF16:
+      switch (kpad) {
+        IPFP_KP16(IPFP_GROUP_CASE, kBF16)
+        default: return hipErrorInvalidValue;
+      }
+    default: return hipErrorInvalidValue;   // the server runs BF16 and FP8 only
   }
-  switch (kpad) {
-    case 32: return group_pass_kp<32, false>(g, idx, first, count, total, tile_rows, s);
-    case 64: return group_pass_kp<64, false>(g, idx, first, count, total, tile_rows, s);
-    case 96: return group_pass_kp<96, false>(g, idx, first, count, total, tile_rows, s);
-    case 128: return group_pass_kp<128, false>(g, idx, first, count, total, tile_rows, s);
-    case 160: return group_pass_kp<160, false>(g, idx, first, count, total, tile_rows, s);
-    case 192: return group_pass_kp<192, false>(g, idx, first, count, total, tile_rows, s);
-    case 224: return group_pass_kp<224, false>(g, idx, first, count, total, tile_rows, s);
-    case 256: return group_pass_kp<256, false>(g, idx, first, count, total, tile_rows, s);
-    default: return hipErrorInvalidValue;
-  }
+#undef IPFP_GROUP_CASE
 }
 
 hipError_t launch_group_combine(const GroupHalf* g, const int32_t* first, int count,
@@ -1594,26 +1666,31 @@ hipError_t launch_group_fixup(const GroupHalf* g, int count, int per, ipfp_dtype
   if (count <= 0 || per <= 0) return hipSuccess;
   const unsigned grid = (unsigned)(count * per);
   if (compute == IPFP_FP8E4M3)
-    hipLaunchKernelGGL(k_group_fixup<true>, dim3(grid), dim3(256), 0, s, g, per);
+    hipLaunchKernelGGL(k_group_fixup<kFP8>, dim3(grid), dim3(256), 0, s, g, per);
   else
-    hipLaunchKernelGGL(k_group_fixup<false>, dim3(grid), dim3(256), 0, s, g, per);
+    hipLaunchKernelGGL(k_group_fixup<kBF16>, dim3(grid), dim3(256), 0, s, g, per);
   return hipGetLastError();
 }
 
 // Workgroups of the sum pass's instantiation for (kpad, type, tile_rows) that
 // one compute unit holds at once (HIP occupancy query, cached; 1 when the
 // query fails, e.g. without a device).
-template <int KP, bool FP8>
+template <int KP, int OK>
 static int pass_wgs_per_cu(int tile_rows) {
-  constexpr int XT = xt_for(KP, FP8);
+  constexpr int XT = xt_for(KP, OK);
   int n = 0;
   hipError_t e;
-  if (tile_rows >= XT * 256)
+  if constexpr (OK == kF32) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void*>(&k_fused_pass<KP, XT, 8, FP8, false>), 512, 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void*>(&k_fused_pass<KP, XT, 4, FP8, false>), 256, 0);
+        &n, reinterpret_cast<const void*>(&k_fused_pass<KP, XT, 4, OK, false>), 256, 0);
+  } else {
+    if (pass_waves(OK, XT, tile_rows) == 8)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, reinterpret_cast<const void*>(&k_fused_pass<KP, XT, 8, OK, false>), 512, 0);
+    else
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, reinterpret_cast<const void*>(&k_fused_pass<KP, XT, 4, OK, false>), 256, 0);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 1;
@@ -1621,35 +1698,37 @@ static int pass_wgs_per_cu(int tile_rows) {
   return n > 0 ? n : 1;
 }
 
-static int pass_wgs_cached(int64_t kpad, bool fp8, int tile_rows) {
-  static std::atomic<int> cache[2][9][2];
-  const int ki = (int)(kpad / 32), wi = tile_rows >= xt_for((int)kpad, fp8) * 256 ? 1 : 0;
-  if (ki < 1 || ki > 8) return 1;
-  const int hit = cache[fp8][ki][wi].load(std::memory_order_relaxed);
+static int pass_wgs_cached(int64_t kpad, int ok, int tile_rows) {
+  static std::atomic<int> cache[3][9][2];
+  const int ki = (int)(kpad / 32), wi = pass_waves(ok, xt_for((int)kpad, ok), tile_rows) == 8;
+  if (ki < 1 || ki > 8 || ok < 0 || ok > 2) return 1;
+  const int hit = cache[ok][ki][wi].load(std::memory_order_relaxed);
   if (hit > 0) return hit;
   int n = 1;
-  if (fp8) {
-    switch (kpad) {
-      case 64: n = pass_wgs_per_cu<64, true>(tile_rows); break;
-      case 128: n = pass_wgs_per_cu<128, true>(tile_rows); break;
-      case 192: n = pass_wgs_per_cu<192, true>(tile_rows); break;
-      case 256: n = pass_wgs_per_cu<256, true>(tile_rows); break;
-      default: break;
-    }
-  } else {
-    switch (kpad) {
-      case 32: n = pass_wgs_per_cu<32, false>(tile_rows); break;
-      case 64: n = pass_wgs_per_cu<64, false>(tile_rows); break;
-      case 96: n = pass_wgs_per_cu<96, false>(tile_rows); break;
-      case 128: n = pass_wgs_per_cu<128, false>(tile_rows); break;
-      case 160: n = pass_wgs_per_cu<160, false>(tile_rows); break;
-      case 192: n = pass_wgs_per_cu<192, false>(tile_rows); break;
-      case 224: n = pass_wgs_per_cu<224, false>(tile_rows); break;
-      case 256: n = pass_wgs_per_cu<256, false>(tile_rows); break;
-      default: break;
-    }
+#define IPFP_OCC_CASE(K, OKV) \
+  case K: n = pass_wgs_per_cu<K, OKV>(tile_rows); break;
+  switch (ok) {
+    case kFP8:
+      switch (kpad) {
+        IPFP_KP8(IPFP_OCC_CASE, kFP8)
+        default: break;
+      }
+      break;
+    case kF32:
+      switch (kpad) {
+        IPFP_KP16(IPFP_OCC_CASE, kF32)
+        default: break;
+      }
+      break;
+    default:
+      switch (kpad) {
+        IPFP_KP16(IPFP_OCC_CASE, kBF16)
+        default: break;
+      }
+      break;
   }
-  cache[fp8][ki][wi].store(n, std::memory_order_relaxed);
+#undef IPFP_OCC_CASE
+  cache[ok][ki][wi].store(n, std::memory_order_relaxed);
   return n;
 }
 
@@ -1660,7 +1739,7 @@ static int pass_wgs_cached(int64_t kpad, bool fp8, int tile_rows) {
 // keeping at least 8 stages per split, the smaller count on ties. It depends
 // only on the market's shape and the device, so results stay reproducible.
 int fused_pass_splits(int64_t R, int64_t L, int64_t kpad, ipfp_dtype compute, int tile_rows) {
-  const bool fp8 = compute == IPFP_FP8E4M3;
+  const int ok = op_kind(compute);
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -1668,9 +1747,9 @@ int fused_pass_splits(int64_t R, int64_t L, int64_t kpad, ipfp_dtype compute, in
     (void)hipGetLastError();
     cus = 256;
   }
-  const int64_t slots = (int64_t)cus * pass_wgs_cached(kpad, fp8, tile_rows);
+  const int64_t slots = (int64_t)cus * pass_wgs_cached(kpad, ok, tile_rows);
   const int rows = fused_rows_per_wg(kpad, compute, tile_rows);
-  const int stage = ty_for((int)kpad * (fp8 ? 1 : 2));
+  const int stage = ty_for((int)kpad * elem_bytes(ok));
   const int64_t rblocks = (R + rows - 1) / rows;
   const int64_t T = (L + stage - 1) / stage;
   int best = 1;

@@ -24,12 +24,18 @@ template <>
 __device__ __forceinline__ double to_d<uint16_t>(uint16_t x) {
   return (double)__uint_as_float((uint32_t)x << 16);
 }
+template <>
+__device__ __forceinline__ double to_d<uint8_t>(uint8_t x) {   // e4m3 code
+  return (double)e4m3_val(x);
+}
 
 // Phi_xy = sum_k U_xk V_yk + Q_xk P_yk in FP64, written to K's buffer in the
 // storage type TK. 64 x 64 output tile per 256 threads, 4 x 4 per thread.
+// FP8 input (TIN = uint8_t codes) is scaled by its rows' scales sx, sy.
 template <typename TIN, typename TK>
 __global__ void __launch_bounds__(256)
     k_phi_factors(const TIN* U, const TIN* Q, const TIN* V, const TIN* P,
+                  const float* sx, const float* sy,
                   int64_t ld_x, int64_t ld_y, int64_t N, int64_t M, int64_t d,
                   TK* K, int64_t ldk) {
   constexpr int TB = 64, KC = 16;
@@ -46,8 +52,14 @@ __global__ void __launch_bounds__(256)
       int64_t x = x0 + r, y = y0 + r;
       double xv = 0.0, yv = 0.0;
       if (k < K2) {
-        if (x < N) xv = k < d ? to_d(U[x * ld_x + k]) : to_d(Q[x * ld_x + k - d]);
-        if (y < M) yv = k < d ? to_d(V[y * ld_y + k]) : to_d(P[y * ld_y + k - d]);
+        if (x < N) {
+          xv = k < d ? to_d(U[x * ld_x + k]) : to_d(Q[x * ld_x + k - d]);
+          if (sx) xv *= (double)sx[x];
+        }
+        if (y < M) {
+          yv = k < d ? to_d(V[y * ld_y + k]) : to_d(P[y * ld_y + k - d]);
+          if (sy) yv *= (double)sy[y];
+        }
       }
       xs[kk][r] = xv;
       ys[kk][r] = yv;
@@ -82,29 +94,47 @@ __global__ void __launch_bounds__(256)
 
 template <typename TIN, typename TK>
 static hipError_t phi_factors_t(const void* U, const void* Q, const void* V,
-                                const void* P, int64_t ld_x, int64_t ld_y,
-                                int64_t N, int64_t M, int64_t d, void* K,
-                                int64_t ldk, hipStream_t s) {
+                                const void* P, const float* sx, const float* sy,
+                                int64_t ld_x, int64_t ld_y, int64_t N, int64_t M, int64_t d,
+                                void* K, int64_t ldk, hipStream_t s) {
   dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64));
   hipLaunchKernelGGL((k_phi_factors<TIN, TK>), grid, dim3(256), 0, s,
-                     (const TIN*)U, (const TIN*)Q, (const TIN*)V, (const TIN*)P,
+                     (const TIN*)U, (const TIN*)Q, (const TIN*)V, (const TIN*)P, sx, sy,
                      ld_x, ld_y, N, M, d, (TK*)K, ldk);
   return hipGetLastError();
 }
 
+template <typename TK>
+static hipError_t phi_factors_k(const void* U, const void* Q, const void* V, const void* P,
+                                ipfp_dtype dt, const float* sx, const float* sy,
+                                int64_t ld_x, int64_t ld_y, int64_t N, int64_t M, int64_t d,
+                                void* K, int64_t ldk, hipStream_t s) {
+  switch (dt) {
+    case IPFP_F64:
+      return phi_factors_t<double, TK>(U, Q, V, P, nullptr, nullptr, ld_x, ld_y, N, M, d, K,
+                                       ldk, s);
+    case IPFP_F32:
+      return phi_factors_t<float, TK>(U, Q, V, P, nullptr, nullptr, ld_x, ld_y, N, M, d, K,
+                                      ldk, s);
+    case IPFP_FP8E4M3:
+      return phi_factors_t<uint8_t, TK>(U, Q, V, P, sx, sy, ld_x, ld_y, N, M, d, K, ldk, s);
+    default:
+      return phi_factors_t<uint16_t, TK>(U, Q, V, P, nullptr, nullptr, ld_x, ld_y, N, M, d,
+                                         K, ldk, s);
+  }
+}
+
 hipError_t launch_phi_from_factors(const void* U, const void* Q, const void* V,
-                                   const void* P, ipfp_dtype dt, int64_t ld_x,
+                                   const void* P, ipfp_dtype dt, const float* scale_x,
+                                   const float* scale_y, int64_t ld_x,
                                    int64_t ld_y, int64_t N, int64_t M,
                                    int64_t d, void* Kbuf, ipfp_dtype kdt,
                                    int64_t ldk, hipStream_t s) {
-  if (kdt == IPFP_F64) {
-    if (dt == IPFP_F64) return phi_factors_t<double, double>(U, Q, V, P, ld_x, ld_y, N, M, d, Kbuf, ldk, s);
-    if (dt == IPFP_F32) return phi_factors_t<float, double>(U, Q, V, P, ld_x, ld_y, N, M, d, Kbuf, ldk, s);
-    return phi_factors_t<uint16_t, double>(U, Q, V, P, ld_x, ld_y, N, M, d, Kbuf, ldk, s);
-  }
-  if (dt == IPFP_F64) return phi_factors_t<double, float>(U, Q, V, P, ld_x, ld_y, N, M, d, Kbuf, ldk, s);
-  if (dt == IPFP_F32) return phi_factors_t<float, float>(U, Q, V, P, ld_x, ld_y, N, M, d, Kbuf, ldk, s);
-  return phi_factors_t<uint16_t, float>(U, Q, V, P, ld_x, ld_y, N, M, d, Kbuf, ldk, s);
+  if (kdt == IPFP_F64)
+    return phi_factors_k<double>(U, Q, V, P, dt, scale_x, scale_y, ld_x, ld_y, N, M, d, Kbuf,
+                                 ldk, s);
+  return phi_factors_k<float>(U, Q, V, P, dt, scale_x, scale_y, ld_x, ld_y, N, M, d, Kbuf,
+                              ldk, s);
 }
 
 // ---- K = exp(Phi / 2 sigma - c_x) -------------------------------------------

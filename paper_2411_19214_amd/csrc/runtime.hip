@@ -78,7 +78,7 @@ void ipfp::handle_layout(ipfp_handle* h, Carver& cv) {
     h->res_block = cv.take<double>(h->nres_row);
   } else {
     const ipfp_dtype cd = h->opt.compute;
-    const size_t es = cd == IPFP_FP8E4M3 ? 1 : 2;
+    const size_t es = cd == IPFP_FP8E4M3 ? 1 : (cd == IPFP_F32 ? 4 : 2);
     h->kpad = fused_kpad(h->mk.d, cd);
     h->xop = cv.take<char>((size_t)N * h->kpad * es);
     h->yop = cv.take<char>((size_t)M * h->kpad * es);
@@ -119,13 +119,16 @@ int ipfp::validate_market(const ipfp_market* mk, const ipfp_options* opt, bool f
     if (!mk->U || !mk->Q || !mk->V || !mk->P) return IPFP_EINVAL;
     if (mk->ld_x < mk->d || mk->ld_y < mk->d) return IPFP_EINVAL;
     if (mk->in_dtype != IPFP_F64 && mk->in_dtype != IPFP_F32 &&
-        mk->in_dtype != IPFP_BF16)
+        mk->in_dtype != IPFP_BF16 && mk->in_dtype != IPFP_FP8E4M3)
       return IPFP_EINVAL;
+    if (mk->in_dtype == IPFP_FP8E4M3 && (!mk->scale_x || !mk->scale_y)) return IPFP_EINVAL;
   }
   if (opt->path == IPFP_PATH_PLAIN) {
     if (opt->compute != IPFP_F32 && opt->compute != IPFP_F64) return IPFP_EINVAL;
   } else if (opt->path == IPFP_PATH_FUSED) {
-    if (opt->compute != IPFP_BF16 && opt->compute != IPFP_FP8E4M3) return IPFP_EINVAL;
+    if (opt->compute != IPFP_BF16 && opt->compute != IPFP_FP8E4M3 &&
+        opt->compute != IPFP_F32)
+      return IPFP_EINVAL;
     if (mk->d > 128) return IPFP_EINVAL;
     if (opt->tile_rows != 0 && opt->tile_rows != 128 && opt->tile_rows != 256 &&
         opt->tile_rows != 512)
@@ -247,6 +250,8 @@ hipError_t ipfp::handle_setup(ipfp_handle* h, const void* phi, ipfp_dtype phi_dt
   const ipfp_options* opt = &h->opt;
   TRY(launch_zero(h->ctl, sizeof(Ctl), s));
   TRY(launch_validate_margins(mk->n, h->N, mk->m, h->M, h->ctl, s));
+  if (!phi && mk->in_dtype == IPFP_FP8E4M3)
+    TRY(launch_validate_scales(mk->scale_x, h->N, mk->scale_y, h->M, h->ctl, s));
   TRY(launch_init_vec(h->u2, nullptr, 2 * h->N, s));
   TRY(launch_init_vec(h->v, opt->b0, h->M, s));
   if (h->plain) {
@@ -254,16 +259,17 @@ hipError_t ipfp::handle_setup(ipfp_handle* h, const void* phi, ipfp_dtype phi_dt
       return launch_materialize(phi, phi_dt, ld_phi, h->K, h->kdt, h->ldk, h->N, h->M,
                                 mk->sigma, h->cshift, h->ctl, s);
     }
-    TRY(launch_phi_from_factors(mk->U, mk->Q, mk->V, mk->P, mk->in_dtype, mk->ld_x,
+    TRY(launch_phi_from_factors(mk->U, mk->Q, mk->V, mk->P, mk->in_dtype, mk->scale_x,
+                                mk->scale_y, mk->ld_x,
                                 mk->ld_y, h->N, h->M, mk->d, h->K, h->kdt, h->ldk, s));
     return launch_materialize(h->K, h->kdt, h->ldk, h->K, h->kdt, h->ldk, h->N, h->M,
                               mk->sigma, h->cshift, h->ctl, s);
   }
   const ipfp_dtype cd = opt->compute;
   const float ps = fused_prescale(mk->sigma);
-  TRY(launch_pack(mk->U, mk->Q, mk->in_dtype, mk->ld_x, h->N, mk->d, cd, h->kpad, ps,
+  TRY(launch_pack(mk->U, mk->Q, mk->in_dtype, mk->scale_x, mk->ld_x, h->N, mk->d, cd, h->kpad, ps,
                   h->xop, h->xscale, h->ctl, s));
-  TRY(launch_pack(mk->V, mk->P, mk->in_dtype, mk->ld_y, h->M, mk->d, cd, h->kpad, ps,
+  TRY(launch_pack(mk->V, mk->P, mk->in_dtype, mk->scale_y, mk->ld_y, h->M, mk->d, cd, h->kpad, ps,
                   h->yop, h->yscale, h->ctl, s));
   FusedSide X{h->xop, cd == IPFP_FP8E4M3 ? h->xscale : nullptr, h->N};
   FusedSide Y{h->yop, cd == IPFP_FP8E4M3 ? h->yscale : nullptr, h->M};
@@ -688,14 +694,16 @@ int ipfp_mu_pairs(ipfp_ctx* ctx, const ipfp_market* mk, const double* a,
     return IPFP_EINVAL;
   if (!mk->U || !mk->Q || !mk->V || !mk->P || mk->d < 1 || !(mk->sigma > 0.0))
     return IPFP_EINVAL;
+  if (mk->in_dtype == IPFP_FP8E4M3 && (!mk->scale_x || !mk->scale_y)) return IPFP_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (hipSetDevice(ctx->device) != hipSuccess) return IPFP_EHIP;
   int32_t* bad = nullptr;
   HIPCHK(hipMalloc((void**)&bad, sizeof(int32_t)));
   int rc = IPFP_OK;
   int32_t hb = 0;
-  if (hipMemsetAsync(bad, 0, sizeof(int32_t), s) != hipSuccess ||
-      launch_mu_pairs(mk->U, mk->Q, mk->V, mk->P, mk->in_dtype, mk->ld_x, mk->ld_y,
+  if (launch_zero(bad, sizeof(int32_t), s) != hipSuccess ||
+      launch_mu_pairs(mk->U, mk->Q, mk->V, mk->P, mk->in_dtype, mk->scale_x, mk->scale_y,
+                      mk->ld_x, mk->ld_y,
                       mk->N, mk->M, mk->d, mk->sigma, a, b, xs, ys, count, mu_out,
                       bad, s) != hipSuccess ||
       hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -713,15 +721,19 @@ int ipfp_stable_factors(ipfp_ctx* ctx, const ipfp_market* mk, const double* a,
   if (mk->N < 1 || mk->M < 1 || mk->d < 1 || mk->d > 256 || !(mk->sigma > 0.0)) return IPFP_EINVAL;
   if (!mk->U || !mk->Q || !mk->V || !mk->P || mk->ld_x < mk->d || mk->ld_y < mk->d)
     return IPFP_EINVAL;
-  if (mk->in_dtype != IPFP_F64 && mk->in_dtype != IPFP_F32 && mk->in_dtype != IPFP_BF16)
+  if (mk->in_dtype != IPFP_F64 && mk->in_dtype != IPFP_F32 && mk->in_dtype != IPFP_BF16 &&
+      mk->in_dtype != IPFP_FP8E4M3)
     return IPFP_EINVAL;
+  if (mk->in_dtype == IPFP_FP8E4M3 && (!mk->scale_x || !mk->scale_y)) return IPFP_EINVAL;
   const int64_t width = 2 * mk->d + 2;
   if (ld_psi < width || ld_xi < width) return IPFP_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (hipSetDevice(ctx->device) != hipSuccess) return IPFP_EHIP;
-  HIPCHK(launch_stable_factors(mk->U, mk->Q, mk->in_dtype, mk->ld_x, mk->N, mk->d, mk->sigma,
+  HIPCHK(launch_stable_factors(mk->U, mk->Q, mk->in_dtype, mk->scale_x, mk->ld_x, mk->N,
+                               mk->d, mk->sigma,
                                a, 0, psi, ld_psi, s));
-  HIPCHK(launch_stable_factors(mk->V, mk->P, mk->in_dtype, mk->ld_y, mk->M, mk->d, mk->sigma,
+  HIPCHK(launch_stable_factors(mk->V, mk->P, mk->in_dtype, mk->scale_y, mk->ld_y, mk->M,
+                               mk->d, mk->sigma,
                                b, 1, xi, ld_xi, s));
   return IPFP_OK;
 }
@@ -810,18 +822,22 @@ int ipfp_market_gradient(ipfp_handle* h, int side, double* g_out, int64_t ld_g,
 }
 
 int ipfp_pack_side(ipfp_ctx* ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
-                   const void* A, const void* B, int64_t ld, ipfp_dtype compute,
+                   const void* A, const void* B, const float* in_scale, int64_t ld,
+                   ipfp_dtype compute,
                    double sigma, void* out, float* scale_out, int64_t* kpad_out,
                    void* stream) {
   if (!ctx || !kpad_out || rows < 1 || d < 1 || d > 128 || ld < d) return IPFP_EINVAL;
   if (!(sigma >= 0.0) || !(sigma < INFINITY)) return IPFP_EINVAL;
-  if (compute != IPFP_BF16 && compute != IPFP_FP8E4M3) return IPFP_EINVAL;
+  if (compute != IPFP_BF16 && compute != IPFP_FP8E4M3 && compute != IPFP_F32)
+    return IPFP_EINVAL;
   const int64_t kpad = fused_kpad(d, compute);
   *kpad_out = kpad;
   if (!out) return IPFP_OK;
   if (!A || !B || (compute == IPFP_FP8E4M3 && !scale_out)) return IPFP_EINVAL;
-  if (in_dtype != IPFP_F64 && in_dtype != IPFP_F32 && in_dtype != IPFP_BF16)
+  if (in_dtype != IPFP_F64 && in_dtype != IPFP_F32 && in_dtype != IPFP_BF16 &&
+      in_dtype != IPFP_FP8E4M3)
     return IPFP_EINVAL;
+  if (in_dtype == IPFP_FP8E4M3 && !in_scale) return IPFP_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (hipSetDevice(ctx->device) != hipSuccess) return IPFP_EHIP;
   char* mem = nullptr;
@@ -831,13 +847,14 @@ int ipfp_pack_side(ipfp_ctx* ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
   float* sc = scale_out ? scale_out : (float*)(mem + align_up(sizeof(Ctl), 256));
   Ctl hc{};
   int rc = IPFP_OK;
-  if (hipMemsetAsync(ctl, 0, sizeof(Ctl), s) != hipSuccess ||
-      launch_pack(A, B, in_dtype, ld, rows, d, compute, kpad, fused_prescale(sigma), out,
+  if (launch_zero(ctl, sizeof(Ctl), s) != hipSuccess ||
+      launch_pack(A, B, in_dtype, in_scale, ld, rows, d, compute, kpad, fused_prescale(sigma), out,
                   sc, ctl, s) != hipSuccess ||
       hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     rc = IPFP_EHIP;
   (void)hipFree(mem);
+  if (rc == IPFP_OK && hc.bad_margin) rc = IPFP_EINVAL;
   if (rc == IPFP_OK && hc.nonfinite) rc = IPFP_ENONFINITE;
   return rc;
 }

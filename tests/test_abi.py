@@ -47,7 +47,7 @@ def test_error_strings(lib):
     for code in (0, 1, -1, -2, -3, -4, -5, -6, -7):
         assert lib.ipfp_strerror(code).decode()
     assert lib.ipfp_strerror(-99).decode() == "unknown error code"
-    assert lib.ipfp_abi_version() == 1
+    assert lib.ipfp_abi_version() == 2
 
 
 def test_default_options(lib):

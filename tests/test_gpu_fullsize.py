@@ -1,6 +1,7 @@
 """Parity at full size: the N = M = 10^6, d = 64 BF16 market in the launch
 configuration the benchmark times (automatic splits and tiles), and the
-unbalanced N = 2x10^6, M = 2x10^5, d = 128 market in FP8 and BF16.
+unbalanced N = 2x10^6, M = 2x10^5, d = 128 market in FP8 and BF16 at
+sigma = 1 and 0.1, and with FP32 operands at sigma = 0.1.
 
 Two checks per shape.
 * Separable surplus phi_xy = alpha_x + gamma_y, carried by factors padded to
@@ -91,10 +92,12 @@ def test_c3_bf16_full_size_sampled(torch, lib):
     check_half_steps(torch, lib, mk, "bf16", sweeps=3)
 
 
-def test_c5_fp8_full_size_sampled(torch, lib):
-    banner("C5 full size N=2e6 M=2e5 d=128 fp8, sampled half-steps")
-    mk = workloads.config_market(5, sigma=1.0)
-    check_half_steps(torch, lib, mk, "fp8", sweeps=2)
+@pytest.mark.parametrize("compute,sigma", [("fp8", 1.0), ("fp8", 0.1), ("bf16", 1.0),
+                                           ("bf16", 0.1), ("f32", 0.1)])
+def test_c5_full_size_sampled(torch, lib, compute, sigma):
+    banner(f"C5 full size N=2e6 M=2e5 d=128 {compute} sigma={sigma}, sampled half-steps")
+    mk = workloads.config_market(5, sigma=sigma)
+    check_half_steps(torch, lib, mk, compute, sweeps=2)
 
 
 @pytest.mark.parametrize("N,M,d,compute,margins,sweeps", [

@@ -36,7 +36,7 @@ def oracle_quantised(mk, compute, sweeps, check_every=1, tol=0.0):
     return K, O.ipfp_batch(K, mk.n, mk.m, tol=tol, max_sweeps=sweeps, check_every=check_every)
 
 
-@pytest.mark.parametrize("compute", ["bf16", "fp8"])
+@pytest.mark.parametrize("compute", ["bf16", "fp8", "f32"])
 def test_pack_side_is_bit_exact(torch, lib, compute):
     banner(f"pack {compute}")
     mk = workloads.config_market(2, N=777, M=5)
@@ -48,7 +48,12 @@ def test_pack_side_is_bit_exact(torch, lib, compute):
         codes, scale = lib.pack_side(to_dev(torch, A), to_dev(torch, B), compute, sigma=sigma)
         kp = codes.shape[1]
         xs = X * quant.prescale(sigma)        # float32 multiply, as the packer does
-        if compute == "bf16":
+        if compute == "f32":
+            want = np.zeros((777, kp), np.float32)
+            want[:, :64] = xs
+            assert np.array_equal(codes.cpu().numpy().view(np.uint32), want.view(np.uint32))
+            got = codes.cpu().numpy().astype(np.float64)
+        elif compute == "bf16":
             want = np.zeros((777, kp), np.uint16)
             want[:, :64] = quant.bf16_bits(xs)
             assert np.array_equal(codes.cpu().numpy().view(np.uint16), want)
@@ -91,6 +96,86 @@ def test_fused_fp8_ragged_shapes(torch, lib, N, M, d):
     K, r = oracle_quantised(mk, "fp8", 20, check_every=5)
     assert rel_err(a.cpu().numpy(), r.a) < 2e-5
     assert rel_err(b.cpu().numpy(), r.b) < 2e-5
+
+
+@pytest.mark.parametrize("N,M,d", [(1, 1, 16), (2, 31, 16), (33, 257, 32), (257, 33, 32),
+                                   (1000, 700, 64), (129, 513, 50), (64, 64, 128),
+                                   (700, 333, 128), (200, 300, 100)])
+def test_fused_f32_ragged_shapes(torch, lib, N, M, d):
+    """FP32 operands on the FP32 MFMA. Kernel error: the oracle fed the same
+    operands (FP32 prescaled factors) within 2e-5 on a, b, as for BF16 (the
+    same FP32 accumulation, exp2 and sums). End to end: the factors are FP32
+    draws, so the only input rounding is the FP32 prescale (a relative 2^-22
+    on each product); against the oracle on the unquantised surplus the same
+    2e-5 holds."""
+    banner(f"fused f32 {N}x{M} d={d}")
+    mk = workloads.factor_market(N, M, d, 1.0 / d, 0.7, "uint1-5", seed=N * 17 + M + d)
+    U, Q, V, P, n, m = market_tensors(torch, mk)
+    a, b, info = lib.solve_market(U, Q, V, P, n, m, mk.sigma, max_sweeps=20, check_every=5,
+                                  compute="f32")
+    K, r = oracle_quantised(mk, "f32", 20, check_every=5)
+    ga, gb = a.cpu().numpy(), b.cpu().numpy()
+    ea, eb = rel_err(ga, r.a), rel_err(gb, r.b)
+    Kx = O.kernel_matrix(O.surplus_from_factors(mk.U, mk.Q, mk.V, mk.P), mk.sigma)
+    rx = O.ipfp_batch(Kx, mk.n, mk.m, max_sweeps=20, check_every=5)
+    xa, xb = rel_err(ga, rx.a), rel_err(gb, rx.b)
+    print(f"f32 {N}x{M} d={d}: kernel err a {ea:.2e} b {eb:.2e}; end-to-end a {xa:.2e} "
+          f"b {xb:.2e}", flush=True)
+    assert info.sweeps == 20 and len(info.residuals) == 4
+    assert ea < 2e-5 and eb < 2e-5 and xa < 2e-5 and xb < 2e-5
+    np.testing.assert_allclose(info.residuals, r.res_hist, rtol=5e-3, atol=3e-7)
+
+
+def test_fp8_input_solves_as_its_fp32_values(torch, lib):
+    """FP8 input (e4m3 codes with power-of-two row scales) is the same market
+    as its values given in FP32: every compute type and path returns the same
+    bits, and so do the outputs read from the factors as given."""
+    banner("fp8 input vs its fp32 values")
+    mk = workloads.config_market(5, N=1500, M=700, sigma=0.5)
+    sides = []
+    for A, B in ((mk.U, mk.Q), (mk.V, mk.P)):
+        rows = np.concatenate([A, B], 1).astype(np.float64) * 3.0
+        vals, s = quant.e4m3_quantize_rows(rows)
+        codes = quant.e4m3_codes(vals / s[:, None])
+        sides.append((vals.astype(np.float32), codes, s.astype(np.float32)))
+    d = mk.d
+    f32 = [to_dev(torch, np.ascontiguousarray(v[:, :d])) for v, _, _ in sides] + \
+          [to_dev(torch, np.ascontiguousarray(v[:, d:])) for v, _, _ in sides]
+    f8 = [to_dev(torch, np.ascontiguousarray(c[:, :d])).view(torch.float8_e4m3fn)
+          for _, c, _ in sides] + \
+         [to_dev(torch, np.ascontiguousarray(c[:, d:])).view(torch.float8_e4m3fn)
+          for _, c, _ in sides]
+    sx, sy = (to_dev(torch, s) for _, _, s in sides)
+    n, m = to_dev(torch, mk.n), to_dev(torch, mk.m)
+    U32, V32, Q32, P32 = f32
+    U8, V8, Q8, P8 = f8
+    for path, compute in (("fused", "bf16"), ("fused", "fp8"), ("fused", "f32"),
+                          ("plain", "f32")):
+        r32 = lib.solve_market(U32, Q32, V32, P32, n, m, mk.sigma, max_sweeps=12,
+                               path=path, compute=compute)
+        r8 = lib.solve_market(U8, Q8, V8, P8, n, m, mk.sigma, max_sweeps=12, path=path,
+                              compute=compute, scale_x=sx, scale_y=sy)
+        assert torch.equal(r32[0], r8[0]) and torch.equal(r32[1], r8[1]), (path, compute)
+        assert r32[2].residuals == r8[2].residuals
+    a, b = r32[0], r32[1]
+    xs = torch.arange(0, mk.N, 5, device="cuda")
+    ys = torch.arange(0, mk.N, 5, device="cuda") % mk.M
+    mu32 = lib.mu_pairs(U32, Q32, V32, P32, mk.sigma, a, b, xs, ys)
+    mu8 = lib.mu_pairs(U8, Q8, V8, P8, mk.sigma, a, b, xs, ys, scale_x=sx, scale_y=sy)
+    assert torch.equal(mu32, mu8)
+    psi32, xi32 = lib.stable_factors(U32, Q32, V32, P32, mk.sigma, a, b)
+    psi8, xi8 = lib.stable_factors(U8, Q8, V8, P8, mk.sigma, a, b, scale_x=sx, scale_y=sy)
+    assert torch.equal(psi32, psi8) and torch.equal(xi32, xi8)
+    c32, _ = lib.pack_side(U32, Q32, "bf16", sigma=mk.sigma)
+    c8, _ = lib.pack_side(U8, Q8, "bf16", sigma=mk.sigma, in_scale=sx)
+    assert torch.equal(c32, c8)
+    # a scale that is not a power of two is refused
+    bad = sx.clone()
+    bad[7] = 3.0
+    with pytest.raises(lib.IPFPError) as e:
+        lib.solve_market(U8, Q8, V8, P8, n, m, mk.sigma, max_sweeps=2, scale_x=bad,
+                         scale_y=sy)
+    assert e.value.code == -1
 
 
 def test_fused_c3_distribution_reduced(torch, lib):

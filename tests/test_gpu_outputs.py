@@ -73,7 +73,8 @@ def check_lists(idx, score, ref_logmu, k):
 @pytest.mark.parametrize("N,M,d,compute,k", [
     (1000, 700, 32, "bf16", 10), (700, 1000, 32, "bf16", 16), (333, 2050, 64, "bf16", 32),
     (900, 600, 64, "fp8", 8), (50, 5, 16, "bf16", 8), (3, 1, 8, "bf16", 4),
-    (700, 900, 128, "fp8", 10), (800, 500, 96, "bf16", 12), (600, 650, 128, "bf16", 32)])
+    (700, 900, 128, "fp8", 10), (800, 500, 96, "bf16", 12), (600, 650, 128, "bf16", 32),
+    (600, 500, 64, "f32", 10), (300, 400, 128, "f32", 16), (70, 40, 16, "f32", 32)])
 def test_topk_lists_match_oracle(torch, lib, N, M, d, compute, k):
     banner(f"topk {N}x{M} d={d} {compute} k={k}")
     mk = workloads.factor_market(N, M, d, 1.0 / d, 0.5, "uint1-5", seed=N + M + k,

@@ -9,12 +9,19 @@ over every pair, each against the oracle's mu:
 * mu implied by the solve itself: K of the rounded operands the kernels used
   (2^T with T from the same quantised values, formed by the oracle), times
   the GPU's a_x b_y -- the matching whose margins the solve satisfies.
-Bars: the plain FP32 path within 1e-5 relative on every mu_xy; the fused BF16
-path within 1e-3 RMS relative over pairs on both measures for sigma >= 0.5.
-FP8 and the sigma = 0.1 stress case are reported, not bounded: their error is
-set by the operand rounding (a surplus error of about 2^-9 |terms| sqrt(2d) /
-(2 sigma) in the exponent for BF16), not by the kernels, whose own error the
-parity tests bound."""
+Bars:
+* the plain FP32 path and the fused FP32 path: within 1e-5 relative on every
+  mu_xy as returned;
+* the fused BF16 path: mu as returned within 1e-3 relative on every pair
+  (max, every case, sigma = 0.1 included). That is the matching the library
+  hands out, so the 1e-3 target applies to it. The solve's own matching (K of
+  the BF16 operands) is bounded by its measured RMS and max with a margin of
+  1.5, to catch regressions; at sigma = 0.1 its RMS is 1.5e-3, above 1e-3,
+  because the operand rounding moves every exponent by about
+  2^-9 |terms| sqrt(2d) / (2 sigma);
+* FP8 is reported (its operand rounding, not the kernels, sets its error;
+  the parity tests bound the kernels' own error).
+"""
 import numpy as np
 import pytest
 
@@ -46,16 +53,16 @@ def mu_errors(K, a, b, ref):
 
 
 CASES = [
-    # (config, N, M, sigma, paths, bf16 rms bar)
-    (2, 4000, 4000, None, ("plain", "bf16", "fp8"), 1e-3),
-    (3, 4000, 4000, None, ("plain", "bf16", "fp8"), 1e-3),
-    (5, 8000, 800, 1.0, ("plain", "bf16", "fp8"), 1e-3),
-    (5, 8000, 800, 0.1, ("plain", "bf16", "fp8"), None),
+    # (config, N, M, sigma, paths, bounds on the BF16 solve's matching: RMS, max)
+    (2, 4000, 4000, None, ("plain", "f32", "bf16", "fp8"), (9e-4, 7.2e-3)),
+    (3, 4000, 4000, None, ("plain", "f32", "bf16", "fp8"), (3.2e-4, 2.3e-3)),
+    (5, 8000, 800, 1.0, ("plain", "f32", "bf16", "fp8"), (2.3e-4, 1.2e-3)),
+    (5, 8000, 800, 0.1, ("plain", "f32", "bf16", "fp8"), (2.3e-3, 1.3e-2)),
 ]
 
 
-@pytest.mark.parametrize("cfg,N,M,sigma,paths,bar", CASES)
-def test_precision_against_fp64_factors(torch, lib, cfg, N, M, sigma, paths, bar):
+@pytest.mark.parametrize("cfg,N,M,sigma,paths,solve_bound", CASES)
+def test_precision_against_fp64_factors(torch, lib, cfg, N, M, sigma, paths, solve_bound):
     banner(f"precision C{cfg} {N}x{M} sigma={sigma}")
     mk = workloads.config_market(cfg, N=N, M=M, sigma=sigma)
     K = O.kernel_matrix(O.surplus_from_factors(mk.U, mk.Q, mk.V, mk.P), mk.sigma)
@@ -69,6 +76,10 @@ def test_precision_against_fp64_factors(torch, lib, cfg, N, M, sigma, paths, bar
             a, b, _ = lib.solve_market(*t, mk.sigma, max_sweeps=SWEEPS, path="plain",
                                        compute="f32")
             Ks = K
+        elif p == "f32":
+            a, b, _ = lib.solve_market(*t, mk.sigma, max_sweeps=SWEEPS, compute="f32")
+            Ks = O.kernel_from_log2(quant.packed_rows(A, mk.sigma, p) @
+                                    quant.packed_rows(B, mk.sigma, p).T)
         else:
             a, b, _ = lib.solve_market(*t, mk.sigma, max_sweeps=SWEEPS, compute=p)
             Ks = O.kernel_from_log2(quant.packed_rows(A, mk.sigma, p) @
@@ -81,7 +92,8 @@ def test_precision_against_fp64_factors(torch, lib, cfg, N, M, sigma, paths, bar
               f"mu returned RMS {out_rms:.2e} max {out_max:.2e}; "
               f"mu of the solve RMS {sol_rms:.2e} max {sol_max:.2e}; "
               f"a,b max rel {eab:.2e}", flush=True)
-        if p == "plain":
+        if p in ("plain", "f32"):
             assert out_max < 1e-5
-        elif p == "bf16" and bar is not None:
-            assert out_rms < bar and sol_rms < bar
+        elif p == "bf16":
+            assert out_max < 1e-3
+            assert sol_rms < solve_bound[0] and sol_max < solve_bound[1]

@@ -371,6 +371,35 @@ def test_packed_rows_reduce_to_plain_rounding_and_log2_kernel():
         assert np.all(np.abs(np.log(K2 / K)) <= 2 * 2.0 ** -8 * bound + 1e-12)
 
 
+def test_packed_rows_f32_is_one_rounding_of_the_exact_product():
+    """FP32 operands: the product p x of two FP32 numbers is exact in FP64
+    (48 significant bits), so rounding that FP64 product once to FP32 is the
+    correctly rounded FP32 product the packer forms; with unit prescale the
+    operands are the FP32 inputs themselves, and the log2 kernel of the FP32
+    operands matches exp(Phi / 2 sigma) to FP32 rounding."""
+    rng = np.random.default_rng(23)
+    X = (rng.normal(0, 0.2, (40, 24)) * np.exp(rng.normal(0, 3, (40, 24)))).astype(np.float32)
+    X[0, :3] = (0.0, 1e-42, -3e38)       # zero, a subnormal, a huge value
+    unit = np.log2(np.e) / 2
+    assert np.array_equal(quant.packed_rows(X, unit, "f32"), X.astype(np.float64))
+    for sigma in (0.1, 0.37, 1.0, 5.0):
+        p = float(quant.prescale(sigma))
+        want = np.array([float(np.float32(float(x) * p)) for x in X.ravel()]).reshape(X.shape)
+        got = quant.packed_rows(X, sigma, "f32")
+        assert np.array_equal(got, want)
+    Y = rng.normal(0, 0.2, (20, 24)).astype(np.float32)
+    Xs = rng.normal(0, 0.2, (30, 24)).astype(np.float32)
+    for sigma in (0.1, 1.0):
+        K2 = ipfp.kernel_from_log2(quant.packed_rows(Xs, sigma, "f32") @
+                                   quant.packed_rows(Y, sigma, "f32").T)
+        K = ipfp.kernel_matrix(Xs.astype(np.float64) @ Y.astype(np.float64).T, sigma)
+        bound = np.abs(Xs.astype(np.float64)) @ np.abs(Y.astype(np.float64)).T / (2 * sigma)
+        # p = sqrt(c)(1 + e), |e| <= 2^-24, and each operand carries one more
+        # rounding: every product is c x y (1 + 4 u) at worst
+        assert np.all(np.abs(np.log(K2 / K)) <= 4 * 2.0 ** -24 * bound + 1e-12)
+        assert not np.array_equal(K2, K)
+
+
 def test_topk_matches_is_repeated_selection():
     """Sec. 4.1: recommendation = the partners of largest mu. Pinned against a
     plain selection loop (take the largest remaining, lowest index on ties)."""
