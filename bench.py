@@ -18,6 +18,7 @@ workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c2] [--no-serve]
                     [--no-outputs]
+    python bench.py --probes | --paper | --precision SIGMA | --serve-only
 """
 from __future__ import annotations
 
@@ -141,7 +142,14 @@ def run_outputs(torch, L, h, mk, factors, reps=3, k=10):
 
 
 def run_c2(torch, L, sweeps=500):
-    """Plain FP32 vs fused BF16 on the same 20k x 20k market, fixed sweeps."""
+    """Plain FP32 vs fused BF16 on the same 20k x 20k market: throughput at a
+    fixed number of sweeps, then accuracy against the exact surplus. Each
+    path's own residual is measured against its own K (the plain path's FP32 K,
+    the fused path's BF16-operand K), so both are also checked with
+    ipfp_margin_residuals, which forms Phi in FP64 from the factors as given:
+    the true margin residual (eq. 5) after k sweeps, for both paths. The
+    comparison at equal accuracy is made at the smallest power of ten that
+    both paths' true residuals reach."""
     mk = workloads.config_market(2)
     U, Q, V, P, n, m = factor_tensors(torch, mk)
     out = {}
@@ -157,14 +165,47 @@ def run_c2(torch, L, sweeps=500):
         pe = 2.0 * mk.N * mk.M * sweeps / loop_s
         out[f"{path}_{compute}"] = dict(pair_evals_per_s=pe, sweeps=info.sweeps,
                                         loop_ms=info.loop_ms, setup_ms=info.setup_ms,
-                                        final_res=info.final_res)
-        # time to tol 1e-6 (the configuration's tolerance)
+                                        final_res_own_kernel=info.final_res,
+                                        ms_per_sweep=info.loop_ms / (sweeps + 1))
+        # time to tol 1e-6 against the path's own kernel (the configuration's tolerance)
         a, b, info = L.solve_market(U, Q, V, P, n, m, mk.sigma,
                                     **dict(kw, tol=1e-6, check_every=1))
-        out[f"{path}_{compute}"]["sweeps_to_1e-6"] = info.sweeps
-        out[f"{path}_{compute}"]["ms_to_1e-6"] = info.loop_ms
+        out[f"{path}_{compute}"]["sweeps_to_1e-6_own_kernel"] = info.sweeps
+        out[f"{path}_{compute}"]["ms_to_1e-6_own_kernel"] = info.loop_ms
+        # true margin residuals (row and column, FP64 surplus) after k sweeps
+        traj = []
+        with L.Market(U, Q, V, P, n, m, mk.sigma, tol=0.0, max_sweeps=60, path=path,
+                      compute=compute) as h:
+            done = 0
+            for k in (1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 20, 30, 40, 60):
+                h.run(k - done)
+                done = k
+                a, b, _ = h.read()
+                _, _, mr, mc = L.margin_residuals(U, Q, V, P, n, m, mk.sigma, a, b)
+                traj.append((k, mr, mc))
+        out[f"{path}_{compute}"]["true_residual_after_sweeps"] = [
+            {"sweeps": k, "row": r, "col": c} for k, r, c in traj]
     p, f = out["plain_f32"], out["fused_bf16"]
     out["fused_over_plain"] = f["pair_evals_per_s"] / p["pair_evals_per_s"]
+
+    def floor(rec):
+        return min(max(t["row"], t["col"]) for t in rec["true_residual_after_sweeps"])
+
+    def sweeps_to(rec, tol):
+        for t in rec["true_residual_after_sweeps"]:
+            if max(t["row"], t["col"]) < tol:
+                return t["sweeps"]
+        return None
+
+    common = 10.0 ** np.ceil(np.log10(max(floor(p), floor(f)) * 1.0000001))
+    eq = {"tolerance": common}
+    for key, rec in (("plain_f32", p), ("fused_bf16", f)):
+        k = sweeps_to(rec, common)
+        eq[key] = {"true_residual_floor": floor(rec), "sweeps": k,
+                   "ms": None if k is None else k * rec["ms_per_sweep"]}
+    if eq["plain_f32"]["ms"] and eq["fused_bf16"]["ms"]:
+        eq["fused_speedup"] = eq["plain_f32"]["ms"] / eq["fused_bf16"]["ms"]
+    out["equal_true_margin_accuracy"] = eq
     return out
 
 
@@ -172,7 +213,8 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else None
 
 
-def run_serving(torch, L, count=512, rate_hz=200.0, aging_ms=0.0, lane_blocks=0):
+def run_serving(torch, L, count=512, rate_hz=200.0, aging_ms=0.0, lane_blocks=0,
+                max_sweeps=200, chunk=4, lanes=3):
     """The serving mix: `count` markets (N, M log-uniform in [1e3, 2e5], d = 32,
     sigma in {0.5, 1}, unit margins, tol 1e-6) submitted at Poisson(rate)
     arrival times to one continuous-batching server; factors are generated on
@@ -181,8 +223,8 @@ def run_serving(torch, L, count=512, rate_hz=200.0, aging_ms=0.0, lane_blocks=0)
     log(f"serving: generating {count} markets on the device")
     tens = [workloads.device_request_factors(torch, r) for r in reqs]
     torch.cuda.synchronize()
-    with L.Server(arena_bytes=16 << 30, max_active=256, lanes=3, chunk=4, aging_ms=aging_ms,
-                  lane_blocks=lane_blocks) as srv:
+    with L.Server(arena_bytes=16 << 30, max_active=256, lanes=lanes, chunk=chunk,
+                  aging_ms=aging_ms, lane_blocks=lane_blocks) as srv:
         # load the grouped kernels once, outside the measured window
         w = srv.submit(*workloads.device_request_factors(
             torch, workloads.Request(-1, 0.0, 1000, 1000, 32, 1.0, 1)), 1.0, tol=1e-6)
@@ -197,7 +239,7 @@ def run_serving(torch, L, count=512, rate_hz=200.0, aging_ms=0.0, lane_blocks=0)
                 if now >= due:
                     break
                 time.sleep(min(0.002, (due - now) / 1e3))
-            handles.append(srv.submit(*t, r.sigma, tol=1e-6, max_sweeps=200))
+            handles.append(srv.submit(*t, r.sigma, tol=1e-6, max_sweeps=max_sweeps))
         log("serving: all submitted, waiting")
         for h in handles:
             srv.wait(h)
@@ -207,14 +249,39 @@ def run_serving(torch, L, count=512, rate_hz=200.0, aging_ms=0.0, lane_blocks=0)
     svc = [h.t_done - h.t_admit for h in handles]
     que = [h.t_admit - h.t_submit for h in handles]
     pe = sum(2.0 * h.N * h.M * h.info.sweeps for h in handles)
-    ok = sum(1 for h in handles if h.status == 0)
-    return {"requests": count, "rate_hz": rate_hz, "converged": ok,
+    conv = [h for h in handles if h.status == 0]
+    small = [h for h in handles if h.N * h.M <= 1e8]
+    # requests that stopped at the sweep cap: shape, sigma and the residual
+    # history tail (a steady geometric decay means slow IPFP convergence, a
+    # plateau would mean a precision floor)
+    unconverged = []
+    for r, h in zip(reqs, handles):
+        if h.status == 0:
+            continue
+        res = h.info.residuals
+        unconverged.append({
+            "N": h.N, "M": h.M, "sigma": r.sigma, "status": h.status,
+            "sweeps": h.info.sweeps, "final_res": h.info.final_res,
+            "res_at": {str(k): res[k - 1] for k in (25, 50, 100, 150, len(res))
+                       if 0 < k <= len(res)},
+            "decay_per_sweep_last_50": (res[-1] / res[-51]) ** (1 / 50) if len(res) > 51
+            else None})
+    return {"requests": count, "rate_hz": rate_hz, "max_sweeps": max_sweeps,
+            "converged": len(conv),
             "sojourn_ms_p50": pct(soj, 50), "sojourn_ms_p99": pct(soj, 99),
             "service_ms_p50": pct(svc, 50), "service_ms_p99": pct(svc, 99),
             "queue_ms_p50": pct(que, 50), "queue_ms_p99": pct(que, 99),
+            "converged_only": {
+                "sojourn_ms_p50": pct([h.t_done - h.t_submit for h in conv], 50),
+                "sojourn_ms_p99": pct([h.t_done - h.t_submit for h in conv], 99),
+                "service_ms_p50": pct([h.t_done - h.t_admit for h in conv], 50),
+                "service_ms_p99": pct([h.t_done - h.t_admit for h in conv], 99)},
+            "small_requests_service_ms_p50": pct([h.t_done - h.t_admit for h in small], 50),
+            "small_requests": len(small),
             "makespan_ms": t_end - t0, "pair_evals_per_s": pe / ((t_end - t0) / 1e3),
             "mean_sweeps": float(np.mean([h.info.sweeps for h in handles])),
-            "rounds": st["rounds"], "arena_peak_bytes": st["arena_peak"]}
+            "rounds": st["rounds"], "arena_peak_bytes": st["arena_peak"],
+            "unconverged": unconverged}
 
 
 def run_paper_sweeps(torch, L, sweeps=100):
@@ -245,6 +312,116 @@ def run_paper_sweeps(torch, L, sweeps=100):
     for D in (10, 20, 100):
         one(100_000, D)
     return rows
+
+
+def run_paper_batch_and_memory(torch, L, sweeps=20):
+    """The timing study's other two axes (Sec. 4.2): rows per mini-batch B and
+    memory against N. B is the output-row height of the fused kernel's
+    workgroup tile (128, 256 or 512 rows stand in for the paper's 1, 10 and
+    100: one workgroup processes its rows against the whole other side, as a
+    mini-batch does), timed at N = M = 10^5 and 10^6, D = 50; the result does
+    not depend on it (Z7). Memory: the library's scratch bytes for a market
+    (ipfp_footprint) and the device memory a resident market actually holds
+    (free memory before and after opening it), fused and plain, for N = M from
+    10^2 to 10^6."""
+    rows = []
+    for N in (100_000, 1_000_000):
+        mk = workloads.paper_uniform(N, N, 50)
+        t = factor_tensors(torch, mk)
+        for tr in (128, 256, 512):
+            L.solve_market(*t, mk.sigma, max_sweeps=2, tile_rows=tr)
+            _, _, info = L.solve_market(*t, mk.sigma, max_sweeps=sweeps, tile_rows=tr,
+                                        use_graph=True, check_every=sweeps)
+            rec = {"N": N, "M": N, "D": 50, "tile_rows": tr,
+                   "ms_per_loop": info.loop_ms / (sweeps + 1)}
+            log(f"paper batch sweep {rec}")
+            rows.append(rec)
+        del t
+        torch.cuda.empty_cache()
+    mem = []
+    for N in (100, 1000, 10_000, 100_000, 1_000_000):
+        mk = workloads.paper_uniform(N, N, 50)
+        t = factor_tensors(torch, mk)
+        rec = {"N": N, "M": N, "D": 50}
+        for path, compute in (("fused", "bf16"), ("plain", "f32")):
+            if path == "plain" and N > 100_000:
+                rec["plain_f32_footprint_bytes"] = L.footprint(N, N, 50, path="plain")
+                continue
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info()[0]
+            with L.Market(*t, mk.sigma, max_sweeps=2, path=path, compute=compute) as h:
+                torch.cuda.synchronize()
+                free1 = torch.cuda.mem_get_info()[0]
+                h.run(1)
+            rec[f"{path}_{compute}_footprint_bytes"] = L.footprint(N, N, 50, path=path,
+                                                                   compute=compute)
+            rec[f"{path}_{compute}_device_bytes_held"] = free0 - free1
+        log(f"paper memory {rec}")
+        mem.append(rec)
+        del t
+        torch.cuda.empty_cache()
+    return {"batch": rows, "memory": mem}
+
+
+def run_precision(torch, L, sigma, sweeps=200, samples=1 << 14, chunk=10):
+    """The precision-stress market at full size (N = 2 x 10^6, M = 2 x 10^5,
+    d = 128, m_y = min(Zipf(1.5), 1000)) solved for `sweeps` sweeps with FP32,
+    BF16 and FP8 operands. The FP32 solve is the reference trajectory: BF16 and
+    FP8 are compared with it on every a_x and b_y and on mu at sampled pairs
+    (ipfp_mu_pairs: FP64 surplus from the factors as given, times each solve's
+    a, b), and each solve's true margin residuals (eq. 5, FP64 surplus) are
+    reported."""
+    mk = workloads.config_market(5, sigma=sigma)
+    t = factor_tensors(torch, mk)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(19214)
+    xs = torch.randint(0, mk.N, (samples,), device="cuda", generator=g)
+    ys = torch.randint(0, mk.M, (samples,), device="cuda", generator=g)
+    res = {"N": mk.N, "M": mk.M, "d": mk.d, "sigma": sigma, "sweeps": sweeps,
+           "samples": samples}
+    sol = {}
+    for compute in ("f32", "bf16", "fp8"):
+        t0 = time.perf_counter()
+        with L.Market(*t, mk.sigma, tol=0.0, max_sweeps=sweeps, compute=compute,
+                      use_graph=True, check_every=chunk) as h:
+            done = 0
+            while not h.run(chunk):
+                done += chunk
+                log(f"precision sigma={sigma} {compute}: {done} sweeps")
+            a, b, info = h.read()
+        wall = time.perf_counter() - t0
+        mu = L.mu_pairs(*t[:4], mk.sigma, a, b, xs, ys)
+        _, _, mr, mc = L.margin_residuals(*t, mk.sigma, a, b)
+        sol[compute] = (a, b, mu)
+        res[compute] = {"sweeps": info.sweeps, "loop_ms": info.loop_ms,
+                        "wall_s": wall, "own_residual": info.final_res,
+                        "true_residual_row": mr, "true_residual_col": mc}
+        log(f"precision sigma={sigma} {compute}: {res[compute]}")
+    a0, b0, mu0 = sol["f32"]
+    for compute in ("bf16", "fp8"):
+        a, b, mu = sol[compute]
+        ra = ((a - a0).abs() / a0).cpu().numpy()
+        rb = ((b - b0).abs() / b0).cpu().numpy()
+        rm = ((mu - mu0).abs() / mu0).cpu().numpy()
+        res[compute]["vs_f32"] = {
+            "a_rms": float(np.sqrt(np.mean(ra ** 2))), "a_max": float(ra.max()),
+            "b_rms": float(np.sqrt(np.mean(rb ** 2))), "b_max": float(rb.max()),
+            "mu_rms": float(np.sqrt(np.mean(rm ** 2))), "mu_max": float(rm.max())}
+    return res
+
+
+def run_probes(torch, L):
+    """The roofline probes (ipfp_probe): exp2 results/s, dense MFMA flop/s of
+    the BF16, FP8 and FP32 instructions the fused passes use, and the
+    streaming HBM read rate."""
+    out = {}
+    for kind in ("exp2", "mfma_bf16", "mfma_fp8", "mfma_f32", "hbm_read"):
+        L.probe(kind)
+        rate, ms = L.probe(kind)
+        out[kind] = {"rate": rate, "ms": ms,
+                     "unit": {"exp2": "exp2/s", "hbm_read": "B/s"}.get(kind, "flop/s")}
+        log(f"probe {kind}: {rate:.4g} ({ms:.2f} ms)")
+    return out
 
 
 def cpu_baseline(mk, budget_s=15.0):
@@ -285,7 +462,14 @@ def main():
     ap.add_argument("--lane-blocks", type=int, default=0,
                     help="serving: workgroups per pass a lane admits up to (0 = default)")
     ap.add_argument("--paper", action="store_true",
-                    help="run only the timing study's size and D sweeps (context)")
+                    help="run only the timing study's size, D, batch and memory sweeps")
+    ap.add_argument("--precision", type=float, default=None, metavar="SIGMA",
+                    help="run only the full-size precision report of the stress market "
+                         "at this sigma (FP32 reference vs BF16 and FP8, 200 sweeps)")
+    ap.add_argument("--probes", action="store_true",
+                    help="run only the roofline probes (exp2, MFMA, HBM read)")
+    ap.add_argument("--max-sweeps", type=int, default=200,
+                    help="serving: sweep cap per request")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving mix (testing)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -308,11 +492,20 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.paper:
-        print(json.dumps({"paper_sweeps": run_paper_sweeps(torch, L)}), flush=True)
+        print(json.dumps({"paper_sweeps": run_paper_sweeps(torch, L),
+                          "paper_batch_memory": run_paper_batch_and_memory(torch, L)}),
+              flush=True)
+        return
+    if args.precision is not None:
+        print(json.dumps({"precision": run_precision(torch, L, args.precision)}), flush=True)
+        return
+    if args.probes:
+        print(json.dumps({"probes": run_probes(torch, L)}), flush=True)
         return
     if args.serve_only:
         print(json.dumps({"serving": run_serving(torch, L, aging_ms=args.aging_ms,
-                                                 lane_blocks=args.lane_blocks)}), flush=True)
+                                                 lane_blocks=args.lane_blocks,
+                                                 max_sweeps=args.max_sweeps)}), flush=True)
         return
     cfg = workloads.CONFIGS[3]
     log(f"generating C3 market N=M={args.size} d={cfg['d']}")
@@ -361,7 +554,8 @@ def main():
         line["c2_20k"] = run_c2(torch, L)
     if not args.no_serve:
         log("serving mix: 512 markets, Poisson 200/s")
-        line["serving"] = run_serving(torch, L)
+        line["serving"] = run_serving(torch, L, aging_ms=args.aging_ms,
+                                      lane_blocks=args.lane_blocks, max_sweeps=args.max_sweeps)
     if not args.no_cpu:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(mk)

@@ -247,6 +247,21 @@ int ipfp_mu_pairs(ipfp_ctx *ctx, const ipfp_market *mk, const double *a,
                   const double *b, const int64_t *xs, const int64_t *ys,
                   int64_t count, double *mu_out, void *stream);
 
+/* Margin residuals of eq. 5 for given scalings (a, b), against the surplus
+ * formed in FP64 from the market's factors as given (in_dtype values, not the
+ * fused path's rounded operands): with mu_xy = exp(Phi_xy / (2 sigma)) a_x b_y
+ * (eq. 4),
+ *   row_res[x] = |a_x^2 + sum_y mu_xy - n_x| / n_x,
+ *   col_res[y] = |b_y^2 + sum_x mu_xy - m_y| / m_y,
+ * every mu formed in the log domain and summed in FP64 (O(N M d) FP64 work:
+ * the exact check of any solve, whatever precision it ran in). a (N), b (M):
+ * device FP64, > 0; row_res (N), col_res (M): caller-owned device FP64
+ * outputs; max_row, max_col: host, may be NULL, receive the maxima (the
+ * stream is synchronised). Scratch of 16 bytes is allocated for the call. */
+int ipfp_margin_residuals(ipfp_ctx *ctx, const ipfp_market *mk, const double *a,
+                          const double *b, double *row_res, double *col_res,
+                          double *max_row, double *max_col, void *stream);
+
 /* Stable factors of eq. 11 (Alg. 2's outputs), with which the matching of
  * eq. 4 factorises as log mu_xy = <psi_x, xi_y> / (2 sigma):
  *   psi_x = [U_x, Q_x, 2 sigma log a_x, 1],  xi_y = [V_y, P_y, 1, 2 sigma log b_y].
@@ -306,6 +321,32 @@ int ipfp_pack_side(ipfp_ctx *ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
                    const void *A, const void *B, const float *in_scale, int64_t ld,
                    ipfp_dtype compute, double sigma, void *out, float *scale_out,
                    int64_t *kpad_out, void *stream);
+
+/* ---- roofline probes ------------------------------------------------------
+ *
+ * Measured ceilings of the operations the passes are bound by, taken on the
+ * context's device: one kernel at full occupancy doing only that operation,
+ * timed with HIP events on `stream` after a warm-up launch.
+ *   EXP2: v_exp_f32 results per second; `work` = iterations per thread
+ *         (8 independent chains each).
+ *   MFMA_BF16 / MFMA_FP8 / MFMA_F32: dense flops per second of the fused
+ *         paths' matrix instructions (32x32x16 BF16, 32x32x64 FP8 with unit
+ *         scales, 32x32x2 FP32), four independent accumulators per wave;
+ *         `work` = MFMAs per accumulator.
+ *   HBM_READ: bytes per second of a streaming read (16-byte nontemporal loads,
+ *         lane-contiguous as in the plain path, four in flight per thread) of
+ *         a `work`-byte buffer (a multiple of 32 MiB, allocated for the call
+ *         and charged to the context budget).
+ * *rate_out receives the rate, *ms_out (may be NULL) the timed launch. */
+enum {
+  IPFP_PROBE_EXP2 = 0,
+  IPFP_PROBE_MFMA_BF16 = 1,
+  IPFP_PROBE_MFMA_FP8 = 2,
+  IPFP_PROBE_MFMA_F32 = 3,
+  IPFP_PROBE_HBM_READ = 4
+};
+int ipfp_probe(ipfp_ctx *ctx, int kind, int64_t work, double *rate_out, double *ms_out,
+               void *stream);
 
 /* ---- serving: continuous batching of many markets ------------------------
  *

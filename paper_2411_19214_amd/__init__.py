@@ -22,7 +22,7 @@ from . import _lib
 
 __all__ = ["IPFPError", "Context", "SolveInfo", "solve_market", "solve_market_phi",
            "Market", "mu_pairs", "pack_side", "footprint", "library", "Server", "Request",
-           "clock_ms", "stable_factors"]
+           "clock_ms", "stable_factors", "margin_residuals", "probe"]
 
 _DT = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "fp8": _lib.FP8E4M3,
        "fp8e4m3": _lib.FP8E4M3}
@@ -361,6 +361,24 @@ def mu_pairs(U, Q, V, P, sigma, a, b, xs, ys, stream=None, ctx=None, scale_x=Non
     return out
 
 
+def margin_residuals(U, Q, V, P, n, m, sigma, a, b, stream=None, ctx=None, scale_x=None,
+                     scale_y=None):
+    """Residuals of eq. 5's margin equations for scalings (a, b) against the
+    surplus formed in FP64 from the factors as given (``ipfp_margin_residuals``):
+    (row_res (N), col_res (M), max row, max column)."""
+    torch = _torch()
+    mk = _market_struct(U, Q, V, P, n, m, sigma, scale_x, scale_y)
+    rr = torch.empty(mk.N, dtype=torch.float64, device=U.device)
+    cr = torch.empty(mk.M, dtype=torch.float64, device=U.device)
+    mr, mc = ctypes.c_double(), ctypes.c_double()
+    ctx = ctx or Context.default(U.device.index or 0)
+    _check(library().ipfp_margin_residuals(ctx.handle, ctypes.byref(mk), a.data_ptr(),
+                                           b.data_ptr(), rr.data_ptr(), cr.data_ptr(),
+                                           ctypes.byref(mr), ctypes.byref(mc),
+                                           _stream_ptr(stream)), "ipfp_margin_residuals")
+    return rr, cr, mr.value, mc.value
+
+
 def stable_factors(U, Q, V, P, sigma, a, b, stream=None, ctx=None, scale_x=None,
                    scale_y=None):
     """(psi, xi) of eq. 11: log mu_xy = <psi_x, xi_y> / (2 sigma), FP64."""
@@ -426,6 +444,22 @@ def footprint(N, M, d, path="fused", compute=None, splits=0, tile_rows=0) -> int
     _check(library().ipfp_footprint(ctypes.byref(mk), ctypes.byref(opt), ctypes.byref(out)),
            "ipfp_footprint")
     return out.value
+
+
+_PROBES = {"exp2": (_lib.PROBE_EXP2, 200000), "mfma_bf16": (_lib.PROBE_MFMA_BF16, 40000),
+           "mfma_fp8": (_lib.PROBE_MFMA_FP8, 20000), "mfma_f32": (_lib.PROBE_MFMA_F32, 10000),
+           "hbm_read": (_lib.PROBE_HBM_READ, 16 << 30)}
+
+
+def probe(kind: str, work: int = 0, stream=None, ctx=None):
+    """A roofline probe (``ipfp_probe``): (rate, ms). kind: "exp2" (results/s),
+    "mfma_bf16" / "mfma_fp8" / "mfma_f32" (flop/s), "hbm_read" (bytes/s)."""
+    code, default = _PROBES[kind]
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    ctx = ctx or Context.default(0)
+    _check(library().ipfp_probe(ctx.handle, code, int(work or default), ctypes.byref(rate),
+                                ctypes.byref(ms), _stream_ptr(stream)), "ipfp_probe")
+    return rate.value, ms.value
 
 
 def clock_ms() -> float:

@@ -121,6 +121,10 @@ SIGNATURES = {
     "ipfp_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Market),
                                  ctypes.POINTER(Options), ctypes.POINTER(Options),
                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "ipfp_margin_residuals": (ctypes.c_int, [
+        ctypes.c_void_p, ctypes.POINTER(Market), ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "ipfp_stable_factors": (ctypes.c_int, [
         ctypes.c_void_p, ctypes.POINTER(Market), ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
@@ -142,7 +146,12 @@ SIGNATURES = {
     "ipfp_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "ipfp_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
     "ipfp_clock_ms": (ctypes.c_double, []),
+    "ipfp_probe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                                  ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
 }
+
+PROBE_EXP2, PROBE_MFMA_BF16, PROBE_MFMA_FP8, PROBE_MFMA_F32, PROBE_HBM_READ = 0, 1, 2, 3, 4
 
 _LIB = None
 

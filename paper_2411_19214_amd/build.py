@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libipfp.so")
-SOURCES = ["control.hip", "plain.hip", "fused.hip", "runtime.hip", "serve.hip"]
+SOURCES = ["control.hip", "plain.hip", "fused.hip", "runtime.hip", "serve.hip", "probe.hip"]
 
 ARCH = "gfx950"
 HIPCC_FLAGS = [

@@ -102,6 +102,15 @@ hipError_t launch_mu_pairs(const void* U, const void* Q, const void* V,
                            const int64_t* xs, const int64_t* ys, int64_t count,
                            double* mu, int32_t* bad, hipStream_t s);
 
+// Margin residuals of eq. 5 for the output side (rows of A|B) against the
+// other side (rows of C|D), from the factors as given; max_out (device, may be
+// null) receives their maximum.
+hipError_t launch_margin_residual(const void* A, const void* B, const float* sa, int64_t lda,
+                                  const void* C, const void* D, const float* sc, int64_t ldc,
+                                  ipfp_dtype dt, int64_t R, int64_t L, int64_t d, double sigma,
+                                  const double* w_out, const double* w_red, const double* marg,
+                                  double* res, double* max_out, hipStream_t s);
+
 // plain path (plain.hip)
 hipError_t launch_phi_from_factors(const void* U, const void* Q, const void* V,
                                    const void* P, ipfp_dtype dt, const float* scale_x,

@@ -714,6 +714,43 @@ int ipfp_mu_pairs(ipfp_ctx* ctx, const ipfp_market* mk, const double* a,
   return rc;
 }
 
+int ipfp_margin_residuals(ipfp_ctx* ctx, const ipfp_market* mk, const double* a,
+                          const double* b, double* row_res, double* col_res, double* max_row,
+                          double* max_col, void* stream) {
+  if (!ctx || !mk || !a || !b || !row_res || !col_res) return IPFP_EINVAL;
+  if (mk->N < 1 || mk->M < 1 || mk->d < 1 || mk->d > 256 || !(mk->sigma > 0.0) ||
+      !(mk->sigma < INFINITY))
+    return IPFP_EINVAL;
+  if (!mk->U || !mk->Q || !mk->V || !mk->P || !mk->n || !mk->m || mk->ld_x < mk->d ||
+      mk->ld_y < mk->d)
+    return IPFP_EINVAL;
+  if (mk->in_dtype != IPFP_F64 && mk->in_dtype != IPFP_F32 && mk->in_dtype != IPFP_BF16 &&
+      mk->in_dtype != IPFP_FP8E4M3)
+    return IPFP_EINVAL;
+  if (mk->in_dtype == IPFP_FP8E4M3 && (!mk->scale_x || !mk->scale_y)) return IPFP_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IPFP_EHIP;
+  double* mx = nullptr;
+  HIPCHK(hipMalloc((void**)&mx, 2 * sizeof(double)));
+  double hm[2] = {0.0, 0.0};
+  int rc = IPFP_OK;
+  if (launch_margin_residual(mk->U, mk->Q, mk->scale_x, mk->ld_x, mk->V, mk->P, mk->scale_y,
+                             mk->ld_y, mk->in_dtype, mk->N, mk->M, mk->d, mk->sigma, a, b,
+                             mk->n, row_res, mx, s) != hipSuccess ||
+      launch_margin_residual(mk->V, mk->P, mk->scale_y, mk->ld_y, mk->U, mk->Q, mk->scale_x,
+                             mk->ld_x, mk->in_dtype, mk->M, mk->N, mk->d, mk->sigma, b, a,
+                             mk->m, col_res, mx + 1, s) != hipSuccess ||
+      hipMemcpyAsync(hm, mx, sizeof(hm), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = IPFP_EHIP;
+  (void)hipFree(mx);
+  if (rc == IPFP_OK) {
+    if (max_row) *max_row = hm[0];
+    if (max_col) *max_col = hm[1];
+  }
+  return rc;
+}
+
 int ipfp_stable_factors(ipfp_ctx* ctx, const ipfp_market* mk, const double* a,
                         const double* b, double* psi, int64_t ld_psi, double* xi,
                         int64_t ld_xi, void* stream) {

@@ -139,6 +139,9 @@ def test_null_arguments(lib):
     assert lib.ipfp_market_run(None, 1, None, None) == _lib.EINVAL
     assert lib.ipfp_stable_factors(None, None, None, None, None, 0, None, 0, None) == _lib.EINVAL
     assert lib.ipfp_tune(None, None, None, None, None, None) == _lib.EINVAL
+    assert lib.ipfp_margin_residuals(None, None, None, None, None, None, None, None,
+                                     None) == _lib.EINVAL
+    assert lib.ipfp_probe(None, 0, 1, None, None, None) == _lib.EINVAL
 
 
 def test_noalloc_capacity_matches_the_header(lib):

@@ -52,6 +52,47 @@ def test_stable_factors_reproduce_matching(torch, lib):
     np.testing.assert_allclose(lm, np.log(mu), rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("in_dtype", ["f64", "f32", "fp8"])
+def test_margin_residuals_match_oracle(torch, lib, in_dtype):
+    """eq. 5's margin residuals of a solve's (a, b) against the surplus of the
+    factors as given, FP64 on both sides: a plain FP64 solve stopped early
+    (residuals of order 1e-3) and a fused BF16 one (its margins hold for the
+    rounded operands, so the true residuals show the operand rounding)."""
+    banner(f"margin residuals, {in_dtype} factors")
+    mk = workloads.config_market(2, N=1500, M=1100)
+    sx = sy = None
+    if in_dtype == "fp8":
+        tens, scales = [], []
+        for A, B in ((mk.U, mk.Q), (mk.V, mk.P)):
+            vals, s = quant.e4m3_quantize_rows(np.concatenate([A, B], 1).astype(np.float64))
+            codes = quant.e4m3_codes(vals / s[:, None])
+            d = A.shape[1]
+            tens.append([codes[:, :d], codes[:, d:]])
+            scales.append(s.astype(np.float32))
+            A[...], B[...] = vals[:, :d], vals[:, d:]
+        t = [torch.from_numpy(np.ascontiguousarray(c)).cuda().view(torch.float8_e4m3fn)
+             for c in (tens[0][0], tens[0][1], tens[1][0], tens[1][1])]
+        t += [torch.from_numpy(mk.n).cuda(), torch.from_numpy(mk.m).cuda()]
+        sx, sy = (torch.from_numpy(s).cuda() for s in scales)
+    else:
+        t = market_tensors(torch, mk, torch.float64 if in_dtype == "f64" else torch.float32)
+    K = O.kernel_matrix(O.surplus_from_factors(mk.U, mk.Q, mk.V, mk.P), mk.sigma)
+    for path, compute, sweeps in (("plain", "f64", 4), ("fused", "bf16", 30)):
+        a, b, _ = lib.solve_market(*t, mk.sigma, max_sweeps=sweeps, path=path, compute=compute,
+                                   scale_x=sx, scale_y=sy)
+        rr, cr, mr, mc = lib.margin_residuals(*t, mk.sigma, a, b, scale_x=sx, scale_y=sy)
+        an, bn = a.cpu().numpy(), b.cpu().numpy()
+        want_r = np.abs(an * an + an * (K @ bn) - mk.n) / mk.n
+        want_c = np.abs(bn * bn + bn * (K.T @ an) - mk.m) / mk.m
+        print(f"margin residuals {in_dtype} {path}/{compute}: max row {mr:.3e} col {mc:.3e}",
+              flush=True)
+        np.testing.assert_allclose(rr.cpu().numpy(), want_r, rtol=1e-9, atol=1e-13)
+        np.testing.assert_allclose(cr.cpu().numpy(), want_c, rtol=1e-9, atol=1e-13)
+        assert mr == float(rr.max()) and mc == float(cr.max())
+        assert mr == pytest.approx(O.row_residual(K, an, bn, mk.n), rel=1e-9, abs=1e-13)
+        assert mc == pytest.approx(O.col_residual(K, an, bn, mk.m), rel=1e-9, abs=1e-13)
+
+
 def check_lists(idx, score, ref_logmu, k):
     R, C = ref_logmu.shape
     ref_idx, ref_val = O.topk_matches(ref_logmu, k)
