@@ -18,7 +18,7 @@ workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c2] [--no-serve]
                     [--no-outputs]
-    python bench.py --probes | --paper | --precision SIGMA | --serve-only
+    python bench.py --probes | --paper | --precision SIGMA | --serve-only | --pass c5:fp8
 """
 from __future__ import annotations
 
@@ -38,6 +38,7 @@ import workloads  # noqa: E402
 METRIC = ("IPFP pair-evals/s, fused BF16 vs plain FP32 @ stated margin err; "
           "p99 solve ms")
 PEAK_BF16_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
+PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}   # dense MFMA, per operand type
 PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 # HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE and
 # WRITE_SIZE counters, scaled by what the counters read for a 1 GiB copy; valid
@@ -410,6 +411,26 @@ def run_precision(torch, L, sigma, sweeps=200, samples=1 << 14, chunk=10):
     return res
 
 
+def run_pass(torch, L, spec, steps, warmup):
+    """One configuration's fused reduction pass alone (for profiling and the
+    per-type roofline): spec "c2|c3|c5:bf16|fp8|f32[:sigma]"; the resident
+    market runs warmup + steps sweeps with every pass launch timed."""
+    parts = spec.split(":")
+    cfg, compute = int(parts[0].lstrip("c")), parts[1]
+    sigma = float(parts[2]) if len(parts) > 2 else None
+    mk = workloads.config_market(cfg, sigma=sigma)
+    log(f"pass {spec}: N={mk.N} M={mk.M} d={mk.d}")
+    r = run_fused(torch, L, mk, steps, warmup, compute=compute)
+    launch_s = r["pass_ms"] / r["launches"] / 1e3
+    # both half-sweeps do 4 d N M flops and N M exp2 per launch
+    tf = 4.0 * mk.d * mk.N * mk.M / launch_s / 1e12
+    return {"config": f"C{cfg}", "compute": compute, "N": mk.N, "M": mk.M, "d": mk.d,
+            "sigma": mk.sigma, "launch_ms": launch_s * 1e3, "tflops": tf,
+            "peak_tflops": PEAK_TFLOPS[compute], "frac": tf / PEAK_TFLOPS[compute],
+            "exp2_per_s": mk.N * mk.M / launch_s,
+            "pair_evals_per_s": 2.0 * mk.N * mk.M * steps / (r["ms"] / 1e3)}
+
+
 def run_probes(torch, L):
     """The roofline probes (ipfp_probe): exp2 results/s, dense MFMA flop/s of
     the BF16, FP8 and FP32 instructions the fused passes use, and the
@@ -468,6 +489,8 @@ def main():
                          "at this sigma (FP32 reference vs BF16 and FP8, 200 sweeps)")
     ap.add_argument("--probes", action="store_true",
                     help="run only the roofline probes (exp2, MFMA, HBM read)")
+    ap.add_argument("--pass", dest="pass_spec", default=None, metavar="CFG:TYPE[:SIGMA]",
+                    help="run only one configuration's fused pass, e.g. c5:fp8 (profiling)")
     ap.add_argument("--max-sweeps", type=int, default=200,
                     help="serving: sweep cap per request")
     ap.add_argument("--serve-only", action="store_true",
@@ -501,6 +524,10 @@ def main():
         return
     if args.probes:
         print(json.dumps({"probes": run_probes(torch, L)}), flush=True)
+        return
+    if args.pass_spec:
+        print(json.dumps({"pass": run_pass(torch, L, args.pass_spec, args.steps, args.warmup)}),
+              flush=True)
         return
     if args.serve_only:
         print(json.dumps({"serving": run_serving(torch, L, aging_ms=args.aging_ms,

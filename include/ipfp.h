@@ -115,11 +115,14 @@ typedef struct {
   double tol;            /* stop when the row residual < tol; 0 = never       */
   int32_t max_sweeps;    /* >= 1                                              */
   int32_t check_every;   /* >= 1: residual cadence (and host sync cadence)    */
-  int32_t splits;        /* reduction splits per half-sweep; 0 = automatic
-                            (chosen from the shape and the device's compute
-                            units and occupancy). Results are bitwise
-                            reproducible for fixed splits; across splits
-                            they agree to rounding.                           */
+  int32_t splits;        /* reduction splits of the row half-sweep (and of
+                            the column one unless splits_col is set); 0 =
+                            automatic (chosen from the shape and the device's
+                            compute units and occupancy). Results are bitwise
+                            reproducible for fixed splits; across splits they
+                            agree to rounding.                                */
+  int32_t splits_col;    /* FUSED: splits of the column half-sweep; 0 = as
+                            `splits` (automatic when that is 0)               */
   int32_t tile_rows;     /* FUSED: output rows per workgroup (128, 256 or
                             512); 0 = a per-type default (256 for BF16 with
                             2d = 64 and FP8 up to 2d = 128, else 512). F32
@@ -165,6 +168,20 @@ void ipfp_default_options(ipfp_options *opt);
 int ipfp_footprint(const ipfp_market *mk, const ipfp_options *opt,
                    size_t *bytes_out);
 
+/* How a fused solve of this market with these options would be laid out on
+ * the current device (host-side only, nothing is launched): the packed width,
+ * the workgroup height, the automatic and the chosen reduction splits of each
+ * half-sweep, their grid sizes and the scratch footprint. */
+typedef struct {
+  int64_t kpad;              /* packed operand width (2d rounded up)         */
+  int32_t rows_per_workgroup;
+  int32_t auto_splits_row, auto_splits_col;
+  int32_t splits_row, splits_col;
+  int64_t blocks_row, blocks_col;   /* workgroups of each reduction pass     */
+  size_t footprint_bytes;
+} ipfp_plan;
+int ipfp_plan_market(const ipfp_market *mk, const ipfp_options *opt, ipfp_plan *out);
+
 /* ---- one-call solves ------------------------------------------------------ */
 
 /* Solve a factor market (eq. 8-10). opt->path selects the fused on-the-fly
@@ -196,13 +213,16 @@ int ipfp_solve_market_noalloc(ipfp_ctx *ctx, const ipfp_market *mk,
                               void *stream);
 
 /* Autotuner for the fused path: times whole sweeps of this market (opened on
- * scratch memory, then freed) for 256 and 512 output rows per workgroup and
- * for the automatic reduction-split count, its half and its double, and
- * returns *opt with the fastest tile_rows and splits in *best (splits 0 =
- * automatic) and that sweep time in *best_ms (may be NULL). Results of a
- * solve depend on the choice only through the split count, to rounding
- * (bitwise reproducible for a fixed choice). Callers cache the choice per
- * market shape; the Python binding keeps a JSON cache. */
+ * scratch memory, then freed) over candidate layouts and returns *opt with
+ * the fastest tile_rows, splits and splits_col in *best and that sweep time in
+ * *best_ms (may be NULL). Candidates: workgroup heights 256 and 512 (FP32:
+ * its fixed 128) times the row pass's automatic split count, its half and its
+ * double; then, for the best of those, the column pass's automatic split
+ * count, its half and its double. Results of a solve depend on the choice
+ * only through the split counts, to rounding (bitwise reproducible for a
+ * fixed choice). Callers cache the choice per market shape as multiples of
+ * the automatic counts (ipfp_plan_market); the Python binding keeps a JSON
+ * cache. */
 int ipfp_tune(ipfp_ctx *ctx, const ipfp_market *mk, const ipfp_options *opt,
               ipfp_options *best, double *best_ms, void *stream);
 

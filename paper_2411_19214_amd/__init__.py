@@ -22,7 +22,7 @@ from . import _lib
 
 __all__ = ["IPFPError", "Context", "SolveInfo", "solve_market", "solve_market_phi",
            "Market", "mu_pairs", "pack_side", "footprint", "library", "Server", "Request",
-           "clock_ms", "stable_factors", "margin_residuals", "probe"]
+           "clock_ms", "stable_factors", "margin_residuals", "probe", "plan"]
 
 _DT = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "fp8": _lib.FP8E4M3,
        "fp8e4m3": _lib.FP8E4M3}
@@ -167,7 +167,7 @@ def _market_struct(U, Q, V, P, n, m, sigma, scale_x=None, scale_y=None):
 
 
 def _options(path, compute, tol, max_sweeps, check_every, splits, tile_rows, b0,
-             use_graph, time_passes):
+             use_graph, time_passes, splits_col=0):
     o = _lib.Options()
     library().ipfp_default_options(ctypes.byref(o))
     o.path = _PATH[path]
@@ -176,6 +176,7 @@ def _options(path, compute, tol, max_sweeps, check_every, splits, tile_rows, b0,
     o.max_sweeps = int(max_sweeps)
     o.check_every = int(check_every)
     o.splits = int(splits)
+    o.splits_col = int(splits_col)
     o.tile_rows = int(tile_rows)
     o.b0 = b0.data_ptr() if b0 is not None else None
     o.use_graph = int(bool(use_graph))
@@ -192,7 +193,7 @@ def _info(code, r, hist):
 def solve_market(U, Q, V, P, n, m, sigma, tol=0.0, max_sweeps=100, check_every=1,
                  path="fused", compute=None, splits=0, tile_rows=0, b0=None,
                  use_graph=False, time_passes=False, stream=None, ctx=None, no_alloc=False,
-                 scale_x=None, scale_y=None):
+                 scale_x=None, scale_y=None, splits_col=0):
     """IPFP on the factor market Phi = U V^T + Q P^T; returns (a, b, info).
     ``compute`` is "bf16", "fp8" or "f32" on the fused path, "f32" or "f64"
     (storage of K) on the plain path. FP8 factors (torch.float8_e4m3fn codes)
@@ -209,7 +210,7 @@ def solve_market(U, Q, V, P, n, m, sigma, tol=0.0, max_sweeps=100, check_every=1
         if b0.dtype != torch.float64 or b0.shape != (mk.M,):
             raise ValueError("b0 must be float64 of length M")
     opt = _options(path, compute, tol, max_sweeps, check_every, splits, tile_rows, b0,
-                   use_graph, time_passes)
+                   use_graph, time_passes, splits_col)
     a = torch.empty(mk.N, dtype=torch.float64, device=U.device)
     b = torch.empty(mk.M, dtype=torch.float64, device=U.device)
     hist = (ctypes.c_double * 4096)()
@@ -262,14 +263,14 @@ class Market:
     def __init__(self, U, Q, V, P, n, m, sigma, tol=0.0, max_sweeps=100,
                  check_every=1, path="fused", compute=None, splits=0, tile_rows=0,
                  b0=None, use_graph=False, time_passes=False, stream=None, ctx=None,
-                 scale_x=None, scale_y=None):
+                 scale_x=None, scale_y=None, splits_col=0):
         if compute is None:
             compute = "bf16" if path == "fused" else "f32"
         # the library reads these buffers until close()
         self._keep = (U, Q, V, P, n, m, b0, scale_x, scale_y)
         self._mk = _market_struct(U, Q, V, P, n, m, sigma, scale_x, scale_y)
         self._opt = _options(path, compute, tol, max_sweeps, check_every, splits,
-                             tile_rows, b0, use_graph, time_passes)
+                             tile_rows, b0, use_graph, time_passes, splits_col)
         self.ctx = ctx or Context.default(U.device.index or 0)
         self.device = U.device
         self.stream = stream
@@ -426,6 +427,25 @@ def pack_side(A, B, compute="bf16", sigma=0.0, stream=None, ctx=None, in_scale=N
                               scale.data_ptr() if scale is not None else None,
                               ctypes.byref(kpad), _stream_ptr(stream)), "ipfp_pack_side")
     return out, scale
+
+
+def plan(N, M, d, compute="bf16", splits=0, tile_rows=0, splits_col=0) -> dict:
+    """The fused path's layout of an N x M market on the current device
+    (``ipfp_plan_market``): packed width, workgroup height, automatic and
+    chosen split counts and grid sizes of both half-sweeps, footprint."""
+    mk = _lib.Market()
+    mk.N, mk.M, mk.d = N, M, d
+    mk.in_dtype = _lib.F32
+    mk.U = mk.Q = mk.V = mk.P = 1
+    mk.ld_x = mk.ld_y = d
+    mk.n = mk.m = 1
+    mk.sigma = 1.0
+    opt = _options("fused", compute, 0.0, 1, 1, splits, tile_rows, None, False, False,
+                   splits_col)
+    out = _lib.Plan()
+    _check(library().ipfp_plan_market(ctypes.byref(mk), ctypes.byref(opt), ctypes.byref(out)),
+           "ipfp_plan_market")
+    return {k: getattr(out, k) for k, _ in _lib.Plan._fields_}
 
 
 def footprint(N, M, d, path="fused", compute=None, splits=0, tile_rows=0) -> int:

@@ -35,7 +35,8 @@ class Options(ctypes.Structure):
         ("path", ctypes.c_int), ("compute", ctypes.c_int),
         ("tol", ctypes.c_double),
         ("max_sweeps", ctypes.c_int32), ("check_every", ctypes.c_int32),
-        ("splits", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+        ("splits", ctypes.c_int32), ("splits_col", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32),
         ("b0", ctypes.c_void_p),
         ("use_graph", ctypes.c_int32), ("time_passes", ctypes.c_int32),
     ]
@@ -49,6 +50,16 @@ class Result(ctypes.Structure):
         ("final_res", ctypes.c_double), ("setup_ms", ctypes.c_double),
         ("loop_ms", ctypes.c_double), ("pass_ms", ctypes.c_double),
         ("pass_launches", ctypes.c_int32), ("fixups", ctypes.c_int32),
+    ]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [
+        ("kpad", ctypes.c_int64), ("rows_per_workgroup", ctypes.c_int32),
+        ("auto_splits_row", ctypes.c_int32), ("auto_splits_col", ctypes.c_int32),
+        ("splits_row", ctypes.c_int32), ("splits_col", ctypes.c_int32),
+        ("blocks_row", ctypes.c_int64), ("blocks_col", ctypes.c_int64),
+        ("footprint_bytes", ctypes.c_size_t),
     ]
 
 
@@ -92,6 +103,8 @@ SIGNATURES = {
     "ipfp_destroy": (None, [ctypes.c_void_p]),
     "ipfp_footprint": (ctypes.c_int, [ctypes.POINTER(Market), ctypes.POINTER(Options),
                                       ctypes.POINTER(ctypes.c_size_t)]),
+    "ipfp_plan_market": (ctypes.c_int, [ctypes.POINTER(Market), ctypes.POINTER(Options),
+                                        ctypes.POINTER(Plan)]),
     "ipfp_solve_market": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Market),
                                          ctypes.POINTER(Options), ctypes.POINTER(Result),
                                          ctypes.c_void_p]),

@@ -88,8 +88,9 @@ void ipfp::handle_layout(ipfp_handle* h, Carver& cv) {
     h->yshift = cv.take<float>(M);
     const int tr = h->opt.tile_rows > 0 ? h->opt.tile_rows : fused_default_tile_rows(h->kpad, cd);
     const int rx = fused_rows_per_wg(h->kpad, cd, tr);
+    const int scol = h->opt.splits_col > 0 ? h->opt.splits_col : h->opt.splits;
     int sx = h->opt.splits > 0 ? h->opt.splits : fused_pass_splits(N, M, h->kpad, cd, tr);
-    int sy = h->opt.splits > 0 ? h->opt.splits : fused_pass_splits(M, N, h->kpad, cd, tr);
+    int sy = scol > 0 ? scol : fused_pass_splits(M, N, h->kpad, cd, tr);
     h->xpart = cv.take<double>((size_t)sx * N);
     h->ypart = cv.take<double>((size_t)sy * M);
     h->xfix = cv.take<int32_t>(N);
@@ -114,6 +115,7 @@ int ipfp::validate_market(const ipfp_market* mk, const ipfp_options* opt, bool f
   if (opt->max_sweeps < 1 || opt->check_every < 1) return IPFP_EINVAL;
   if (!(opt->tol >= 0.0)) return IPFP_EINVAL;
   if (opt->splits < 0 || opt->splits > 256) return IPFP_EINVAL;
+  if (opt->splits_col < 0 || opt->splits_col > 256) return IPFP_EINVAL;
   if (factors) {
     if (mk->d < 1 || mk->d > 256) return IPFP_EINVAL;
     if (!mk->U || !mk->Q || !mk->V || !mk->P) return IPFP_EINVAL;
@@ -605,6 +607,36 @@ int ipfp_solve_market_noalloc(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_o
   return rc;
 }
 
+// Sweep time of one candidate layout: open the market (set-up included in no
+// timing), one warm-up sweep, then the mean of two timed sweeps. INFINITY when
+// the candidate does not fit the budget.
+static int time_candidate(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* opt,
+                          int tile_rows, int splits, int splits_col, hipStream_t s,
+                          double* ms) {
+  const int kWarm = 1, kReps = 2;
+  ipfp_options o = *opt;
+  o.tile_rows = tile_rows;
+  o.splits = splits;
+  o.splits_col = splits_col;
+  o.tol = 0.0;
+  o.max_sweeps = kWarm + kReps + 1;
+  o.check_every = kWarm + kReps + 1;
+  o.use_graph = 0;
+  o.time_passes = 0;
+  ipfp_handle* h = nullptr;
+  int rc = open_impl(ctx, mk, &o, nullptr, IPFP_F32, 0, &h, s);
+  *ms = INFINITY;
+  if (rc == IPFP_EBUDGET) return IPFP_OK;   // a candidate that does not fit is skipped
+  if (rc != IPFP_OK) return rc;
+  int done = 0;
+  rc = run_impl(h, kWarm, &done, s);
+  const double before = h->loop_ms;
+  if (rc == IPFP_OK) rc = run_impl(h, kReps, &done, s);
+  if (rc == IPFP_OK) *ms = (h->loop_ms - before) / kReps;
+  destroy_handle(h);
+  return rc;
+}
+
 int ipfp_tune(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* opt,
               ipfp_options* best, double* best_ms, void* stream) {
   if (!ctx || !mk || !opt || !best) return IPFP_EINVAL;
@@ -612,51 +644,73 @@ int ipfp_tune(ipfp_ctx* ctx, const ipfp_market* mk, const ipfp_options* opt,
   int rc = validate_market(mk, opt, true);
   if (rc != IPFP_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
-  // candidates: 256 or 512 output rows per workgroup, times the automatic
-  // split count and its half and double (0 = automatic per pass)
-  std::vector<std::pair<int, int>> cand;
-  for (int tr : {512, 256}) {
-    const int sa = fused_pass_splits(mk->N, mk->M, fused_kpad(mk->d, opt->compute),
-                                     opt->compute, tr);
-    cand.push_back({tr, 0});
-    if (sa / 2 >= 1) cand.push_back({tr, sa / 2});
-    if (sa * 2 <= 256) cand.push_back({tr, sa * 2});
-  }
-  const int kWarm = 1, kReps = 2;
+  const int64_t kpad = fused_kpad(mk->d, opt->compute);
   double best_t = INFINITY;
-  ipfp_options win = *opt;
-  for (const auto& c : cand) {
-    ipfp_options o = *opt;
-    o.tile_rows = c.first;
-    o.splits = c.second;
-    o.tol = 0.0;
-    o.max_sweeps = kWarm + kReps + 1;
-    o.check_every = kWarm + kReps + 1;
-    o.use_graph = 0;
-    o.time_passes = 0;
-    o.b0 = opt->b0;
-    ipfp_handle* h = nullptr;
-    rc = open_impl(ctx, mk, &o, nullptr, IPFP_F32, 0, &h, s);
-    if (rc == IPFP_EBUDGET) continue;   // a candidate that does not fit is skipped
-    if (rc != IPFP_OK) return rc;
-    int done = 0;
-    rc = run_impl(h, kWarm, &done, s);
-    const double before = h->loop_ms;
-    if (rc == IPFP_OK) rc = run_impl(h, kReps, &done, s);
-    const double t = (h->loop_ms - before) / kReps;
-    destroy_handle(h);
-    if (rc != IPFP_OK) return rc;
-    if (t < best_t) {
-      best_t = t;
-      win.tile_rows = c.first;
-      win.splits = c.second;
+  int win_tr = 0, win_sx = 0, win_sy = 0;
+  // stage 1: workgroup height x row-pass splits (column pass automatic)
+  std::vector<int> heights;
+  if (opt->compute == IPFP_F32) heights = {128};
+  else heights = {512, 256};
+  for (int tr : heights) {
+    const int sa = fused_pass_splits(mk->N, mk->M, kpad, opt->compute, tr);
+    for (int sx : {sa, sa / 2, sa * 2}) {
+      if (sx < 1 || sx > 256) continue;
+      double t = 0.0;
+      rc = time_candidate(ctx, mk, opt, tr, sx, 0, s, &t);
+      if (rc != IPFP_OK) return rc;
+      if (t < best_t) {
+        best_t = t;
+        win_tr = tr;
+        win_sx = sx;
+      }
     }
   }
   if (!(best_t < INFINITY)) return IPFP_EBUDGET;
+  // stage 2: column-pass splits for the winner
+  const int sc = fused_pass_splits(mk->M, mk->N, kpad, opt->compute, win_tr);
+  win_sy = sc;
+  for (int sy : {sc / 2, sc * 2}) {
+    if (sy < 1 || sy > 256) continue;
+    double t = 0.0;
+    rc = time_candidate(ctx, mk, opt, win_tr, win_sx, sy, s, &t);
+    if (rc != IPFP_OK) return rc;
+    if (t < best_t) {
+      best_t = t;
+      win_sy = sy;
+    }
+  }
   *best = *opt;
-  best->tile_rows = win.tile_rows;
-  best->splits = win.splits;
+  best->tile_rows = win_tr;
+  best->splits = win_sx;
+  best->splits_col = win_sy;
   if (best_ms) *best_ms = best_t;
+  return IPFP_OK;
+}
+
+int ipfp_plan_market(const ipfp_market* mk, const ipfp_options* opt, ipfp_plan* out) {
+  if (!out) return IPFP_EINVAL;
+  int rc = validate_market(mk, opt, true);
+  if (rc != IPFP_OK) return rc;
+  if (opt->path != IPFP_PATH_FUSED) return IPFP_EINVAL;
+  ipfp_handle h;
+  h.mk = *mk;
+  h.opt = *opt;
+  h.N = mk->N;
+  h.M = mk->M;
+  Carver cv;
+  handle_layout(&h, cv);
+  const int tr = h.rowp.tile_rows;
+  memset(out, 0, sizeof(*out));
+  out->kpad = h.kpad;
+  out->rows_per_workgroup = fused_rows_per_wg(h.kpad, opt->compute, tr);
+  out->auto_splits_row = fused_pass_splits(mk->N, mk->M, h.kpad, opt->compute, tr);
+  out->auto_splits_col = fused_pass_splits(mk->M, mk->N, h.kpad, opt->compute, tr);
+  out->splits_row = h.rowp.splits;
+  out->splits_col = h.colp.splits;
+  const int64_t rows = out->rows_per_workgroup;
+  out->blocks_row = (mk->N + rows - 1) / rows * out->splits_row;
+  out->blocks_col = (mk->M + rows - 1) / rows * out->splits_col;
+  out->footprint_bytes = align_up(cv.off, 256);
   return IPFP_OK;
 }
 

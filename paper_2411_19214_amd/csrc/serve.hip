@@ -544,16 +544,23 @@ bool admit(ipfp_server* srv, Req* r) {
   h->ext_ctl = srv->ctl_pool + slot;
   h->mem = srv->slab + off;
   h->bytes = r->bytes;
-  Carver cv;
-  cv.base = h->mem;
-  handle_layout(h, cv);
   r->h = h;
   r->off = off;
   r->slot = slot;
   const int lane = r->lane_hint;
   Lane& L = srv->lanes[lane];
   L.blocks += r->blocks;
-  hipError_t e = hipStreamWaitEvent(L.s, r->ready, 0);
+  // the layout is carved here, on the scheduler thread: check that it fits the
+  // slice sized at submission before any buffer is placed
+  Carver size_only;
+  handle_layout(h, size_only);
+  hipError_t e = align_up(size_only.off, 256) <= r->bytes ? hipSuccess : hipErrorInvalidValue;
+  if (e == hipSuccess) {
+    Carver cv;
+    cv.base = h->mem;
+    handle_layout(h, cv);
+    e = hipStreamWaitEvent(L.s, r->ready, 0);
+  }
   if (e == hipSuccess) e = handle_setup(h, nullptr, IPFP_F32, 0, L.s);
   {
     std::lock_guard<std::mutex> g(srv->mu);
@@ -830,11 +837,13 @@ int ipfp_submit(ipfp_server* srv, const ipfp_market* mk, const ipfp_options* opt
   o.time_passes = 0;
   int rc = validate_market(mk, &o, true);
   if (rc != IPFP_OK) return rc;
+  // the layout's split counts depend on the current device's compute units and
+  // occupancy: size it with the server's device current, as admission will
+  if (hipSetDevice(srv->ctx->device) != hipSuccess) return IPFP_EHIP;
   size_t bytes = 0;
   rc = ipfp_footprint(mk, &o, &bytes);
   if (rc != IPFP_OK) return rc;
   if (bytes > srv->arena.cap()) return IPFP_EBUDGET;
-  if (hipSetDevice(srv->ctx->device) != hipSuccess) return IPFP_EHIP;
   const int64_t kpad = fused_kpad(mk->d, o.compute);
   const int tr = o.tile_rows > 0 ? o.tile_rows : fused_default_tile_rows(kpad, o.compute);
   const int rx = fused_rows_per_wg(kpad, o.compute, tr);

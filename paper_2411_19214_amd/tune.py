@@ -9,6 +9,9 @@ tuned once per machine:
     opts = tuned(U, Q, V, P, n, m, sigma, compute="bf16")
     a, b, info = solve_market(U, Q, V, P, n, m, sigma, **opts)
 
+The split counts are cached as multiples of the library's automatic counts
+(``plan``), so they carry over to other shapes of the same bucket.
+
 The cache file is ``$IPFP_TUNE_CACHE`` or ``~/.cache/ipfp/tune.json``.
 """
 from __future__ import annotations
@@ -51,18 +54,32 @@ def _store(path, table):
     os.replace(tmp, path)
 
 
+def _apply(choice: dict, N: int, M: int, d: int, compute: str) -> dict:
+    """Solve options for a market of this shape from a cached choice: the
+    split counts are stored as multiples of the automatic counts, so a shape
+    that shares the bucket gets its own automatic count times the multiple."""
+    from . import plan
+    auto = plan(N, M, d, compute=compute, tile_rows=choice["tile_rows"])
+    return {"tile_rows": choice["tile_rows"],
+            "splits": max(1, min(256, round(choice["row_split_mult"] * auto["auto_splits_row"]))),
+            "splits_col": max(1, min(256, round(choice["col_split_mult"] *
+                                                auto["auto_splits_col"])))}
+
+
 def tuned(U, Q, V, P, n, m, sigma, compute="bf16", path=None, refresh=False,
           stream=None, ctx=None) -> dict:
-    """{"tile_rows": ..., "splits": ...} for this market's shape, from the cache
-    or measured on the device (``ipfp_tune``) and then cached."""
-    from . import Context, _check, _market_struct, _options, _stream_ptr, library
+    """{"tile_rows", "splits", "splits_col"} for this market, from the cache or
+    measured on the device (``ipfp_tune``) and then cached (as multiples of
+    the automatic split counts)."""
+    from . import Context, _check, _market_struct, _options, _stream_ptr, library, plan
     import torch
     path = path or cache_path()
     arch = torch.cuda.get_device_properties(U.device).gcnArchName.split(":")[0]
-    key = shape_key(arch, compute, U.shape[1], U.shape[0], V.shape[0])
+    N, d, M = U.shape[0], U.shape[1], V.shape[0]
+    key = shape_key(arch, compute, d, N, M)
     table = _load(path)
     if not refresh and key in table:
-        return dict(table[key]["options"])
+        return _apply(table[key]["choice"], N, M, d, compute)
     mk = _market_struct(U, Q, V, P, n, m, sigma)
     opt = _options("fused", compute, 0.0, 4, 4, 0, 0, None, False, False)
     best = _lib.Options()
@@ -71,8 +88,12 @@ def tuned(U, Q, V, P, n, m, sigma, compute="bf16", path=None, refresh=False,
     _check(library().ipfp_tune(ctx.handle, ctypes.byref(mk), ctypes.byref(opt),
                                ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)),
            "ipfp_tune")
-    choice = {"tile_rows": best.tile_rows, "splits": best.splits}
+    auto = plan(N, M, d, compute=compute, tile_rows=best.tile_rows)
+    choice = {"tile_rows": best.tile_rows,
+              "row_split_mult": best.splits / auto["auto_splits_row"],
+              "col_split_mult": best.splits_col / auto["auto_splits_col"]}
     table = _load(path)
-    table[key] = {"options": choice, "sweep_ms": ms.value}
+    table[key] = {"choice": choice, "sweep_ms": ms.value,
+                  "tuned_shape": [N, M, d], "splits": [best.splits, best.splits_col]}
     _store(path, table)
-    return choice
+    return _apply(choice, N, M, d, compute)

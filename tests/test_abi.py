@@ -144,6 +144,27 @@ def test_null_arguments(lib):
     assert lib.ipfp_probe(None, 0, 1, None, None, None) == _lib.EINVAL
 
 
+def test_plan_reports_the_layout(lib):
+    # without a device the split rule assumes 256 compute units and one resident
+    # workgroup per unit; the plan must agree with the footprint either way
+    o = _opts(lib)
+    mk = _market(200_000, 50_000, 32)
+    p = _lib.Plan()
+    assert lib.ipfp_plan_market(ctypes.byref(mk), ctypes.byref(o), ctypes.byref(p)) == 0
+    assert p.kpad == 64 and p.rows_per_workgroup in (256, 512)
+    assert (p.splits_row, p.splits_col) == (p.auto_splits_row, p.auto_splits_col)
+    assert p.blocks_row == -(-200_000 // p.rows_per_workgroup) * p.splits_row
+    assert p.footprint_bytes == _footprint(lib, mk, o)[1]
+    o2 = _opts(lib, splits=3, splits_col=5)
+    assert lib.ipfp_plan_market(ctypes.byref(mk), ctypes.byref(o2), ctypes.byref(p)) == 0
+    assert (p.splits_row, p.splits_col) == (3, 5)
+    o3 = _opts(lib, splits=3)
+    assert lib.ipfp_plan_market(ctypes.byref(mk), ctypes.byref(o3), ctypes.byref(p)) == 0
+    assert (p.splits_row, p.splits_col) == (3, 3)
+    assert lib.ipfp_plan_market(ctypes.byref(mk), ctypes.byref(_opts(lib, splits_col=-1)),
+                                ctypes.byref(p)) == _lib.EINVAL
+
+
 def test_noalloc_capacity_matches_the_header(lib):
     text = open(HEADER).read()
     m = re.search(r"#define IPFP_NOALLOC_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)

@@ -319,8 +319,16 @@ def test_autotuner_choice_and_cache(torch, lib, tmp_path):
     t = market_tensors(torch, mk)
     path = str(tmp_path / "tune.json")
     opts = tune.tuned(*t, mk.sigma, compute="bf16", path=path)
-    assert opts["tile_rows"] in (256, 512) and 0 <= opts["splits"] <= 256
+    assert opts["tile_rows"] in (256, 512)
+    assert 1 <= opts["splits"] <= 256 and 1 <= opts["splits_col"] <= 256
     assert tune.tuned(*t, mk.sigma, compute="bf16", path=path) == opts   # cached
+    p = lib.plan(mk.N, mk.M, mk.d, tile_rows=opts["tile_rows"], splits=opts["splits"],
+                 splits_col=opts["splits_col"])
+    assert (p["splits_row"], p["splits_col"]) == (opts["splits"], opts["splits_col"])
+    # a shape of the same bucket gets the cached multiples of its own automatic counts
+    other = tune.tuned(*market_tensors(torch, workloads.config_market(2, N=18000, M=13000)),
+                       mk.sigma, compute="bf16", path=path)
+    assert other["tile_rows"] == opts["tile_rows"]
     a0, b0, i0 = lib.solve_market(*t, mk.sigma, max_sweeps=30)
     a1, b1, i1 = lib.solve_market(*t, mk.sigma, max_sweeps=30, **opts)
     # the split count only reorders FP64 partial sums
