@@ -966,9 +966,10 @@ hipError_t launch_topk(const FusedPass& fp, const double* a_out, int k, int spli
 // high and low parts (about 16 significant bits together), times the value
 // tile. The product needs the value rows column-contiguous, so the packed
 // reduced side is first transposed once into a column-major copy (zero past
-// the last row); each stage then copies a block of it into LDS (columns
-// padded by 8 bytes against bank conflicts), and a lane reads its eight K
-// values as two 8-byte loads. The product's K order is a permutation of the
+// the last row); each stage then copies a block of it into LDS, every column
+// split into two halves by bit 2 of the row index (padded by 16 bytes against
+// bank conflicts), so that a lane reads its eight K values as one 16-byte
+// load. The product's K order is a permutation of the
 // 32 reduced rows of a subtile that lets every lane feed its own P values as
 // the B operand. A workgroup (4 waves, one per SIMD: the FP64 sums take the
 // registers of a second) covers 128 output rows and up to four 32-column
@@ -1021,7 +1022,12 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
   constexpr int CH = C::CH, CPT = C::CPT, SUB = C::SUB;
   constexpr int NB = KP / 32;               // 32-column blocks of the value rows
   constexpr int NBL = grad_col_blocks(KP);  // ... handled by one workgroup
-  constexpr int TS = kTY * 2 + 8;           // bytes per staged column
+  // bytes per staged column. A column's rows are stored in two halves by bit 2
+  // of the row index, each in order of (row >> 3, row & 3): the eight rows a
+  // lane feeds one product MFMA (r0..r0+3, r0+8..r0+11 with bit 2 = h) are then
+  // 16 consecutive bytes, read with one ds_read_b128, and a 16-byte pad keeps
+  // the 16 lanes of a read phase on distinct banks
+  constexpr int TS = kTY * 2 + 16;
   constexpr int CCH = kTY * 2 / 16;         // 16-byte chunks per staged column
   constexpr int CHT = NBL * 32 * CCH;
   constexpr int CPTT = (CHT + NT - 1) / NT;
@@ -1096,9 +1102,10 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
     for (int q = 0; q < CPTT; ++q) {
       const int chunk = min(tid + q * NT, CHT - 1);
       const int cl = chunk / CCH, j = chunk % CCH;
-      uint8_t* d = &yt[buf][cl * TS + 16 * j];
+      // rows 8j..8j+3 to the first half, 8j+4..8j+7 to the second
+      uint8_t* d = &yt[buf][cl * TS + 8 * j];
       *reinterpret_cast<int2*>(d) = int2{pret[q][0], pret[q][1]};
-      *reinterpret_cast<int2*>(d + 8) = int2{pret[q][2], pret[q][3]};
+      *reinterpret_cast<int2*>(d + kTY) = int2{pret[q][2], pret[q][3]};
     }
     ws[buf][tid % kTY] = pw;
   };
@@ -1153,19 +1160,14 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
           bl[i] = lv[0];
           bl[i + 1] = lv[1];
         }
-        const int r0 = sub * 32 + 16 * ks + 4 * h;   // rows r0..r0+3, r0+8..r0+11
 #pragma unroll
         for (int nb = 0; nb < NBL; ++nb) {
           if (nb < nbn) {
             // A operand: value column 32 (nb0 + nb) + l32 at the same eight rows
-            const uint8_t* col = &yt[buf][(32 * nb + l32) * TS];
-            intx4 av;
-            const int2 v0 = *reinterpret_cast<const int2*>(col + r0 * 2);
-            const int2 v1 = *reinterpret_cast<const int2*>(col + (r0 + 8) * 2);
-            av[0] = v0.x;
-            av[1] = v0.y;
-            av[2] = v1.x;
-            av[3] = v1.y;
+            // (r0..r0+3, r0+8..r0+11, r0 = 32 sub + 16 ks + 4 h): positions
+            // 16 sub + 8 ks .. + 7 of half h
+            const uint8_t* col = &yt[buf][(32 * nb + l32) * TS + h * kTY + sub * 32 + ks * 16];
+            const intx4 av = *reinterpret_cast<const intx4*>(col);
             const bf16x8 a = *reinterpret_cast<const bf16x8*>(&av);
             g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, g32[nb], 0, 0, 0);
             g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, g32[nb], 0, 0, 0);
