@@ -20,7 +20,8 @@ struct Ctl {
   int32_t nonfinite;    // 1 if a non-finite intermediate was produced
   int32_t bad_margin;   // 1 if a margin was not > 0 and finite, or an FP8
                         // input row scale not a positive power of two
-  int32_t fix_rows;     // rows queued for the exact-shift fallback (this pass)
+  int32_t arrive;       // combine workgroups of the row pass that have finished
+                        // (the last one runs the convergence check)
   int32_t fix_total;    // rows recomputed by the fallback over the solve
   int32_t wexp[2];      // fused path: largest binary exponent of u (0), v (1)
   double last_res;      // most recent recorded residual
@@ -79,6 +80,56 @@ __device__ __forceinline__ T wave_max(T v) {
     v = w > v ? w : v;
   }
   return v;
+}
+
+// One workgroup: reduce the residual maxima of the row pass that just ran
+// (they belong to state i = ctl->sweep), record them at check sweeps, decide
+// whether the solve stops at state i, and otherwise advance to state i + 1.
+// The residual of state i is available here because the row pass of sweep
+// i + 1 computes K v^(i) anyway; u^(i) is kept in the other half of a double
+// buffer, so stopping at i returns exactly (u^(i), v^(i)).
+__device__ __forceinline__ void check_body(Ctl* ctl, const double* res_block, int nblocks,
+                                           double* hist, const SweepParams& sp) {
+  __shared__ double red[256];
+  if (ctl->done) return;
+  const int i = ctl->sweep;
+  const bool chk = is_check(i, sp);
+  double r = 0.0;
+  if (chk) {
+    for (int k = threadIdx.x; k < nblocks; k += blockDim.x) {
+      double x = res_block[k];
+      // NaN compares false: keep it visible
+      r = (x > r || x != x) ? x : r;
+    }
+  }
+  red[threadIdx.x] = r;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      double a = red[threadIdx.x], b = red[threadIdx.x + o];
+      red[threadIdx.x] = (b > a || b != b) ? b : a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (ctl->nonfinite || ctl->bad_margin) {
+    ctl->done = 1;
+    ctl->stop_sweep = i;
+    return;
+  }
+  if (chk) {
+    r = red[0];
+    if (ctl->n_checks < sp.hist_cap) hist[ctl->n_checks] = r;
+    ctl->n_checks += 1;
+    ctl->last_res = r;
+    if (r != r) ctl->nonfinite = 1;
+    if (r < sp.tol || i >= sp.max_sweeps || r != r) {
+      ctl->done = 1;
+      ctl->stop_sweep = i;
+      return;
+    }
+  }
+  ctl->sweep = i + 1;
 }
 
 // ---- launchers implemented in the .hip sources ----------------------------
@@ -159,17 +210,18 @@ struct FusedPass {
   const double* marg;       // out.rows margins
   double* part;             // splits x out.rows partial sums
   double* res_block;        // per-combine-block residual maxima
-  int32_t* fix_list;        // out.rows
   int splits;
   int tile_rows;            // requested output rows per workgroup
   bool residual;            // compute the row residual of the old scaling
 };
 hipError_t launch_fused_pass(const FusedPass& fp, Ctl* ctl, hipStream_t s);
 hipError_t launch_fused_shift(const FusedPass& fp, Ctl* ctl, hipStream_t s);
-hipError_t launch_fused_combine(const FusedPass& fp, double* w2, int dbuf,
-                                Ctl* ctl, int* nblocks, hipStream_t s);
-hipError_t launch_fused_fixup(const FusedPass& fp, double* w2, int dbuf,
-                              double* res_slot, Ctl* ctl, hipStream_t s);
+// Combine of a pass's partial sums, the quadratic update of its output side,
+// the exact fallback for rows out of the shift's range and, for the row pass
+// (fp.residual), the convergence check: one launch.
+hipError_t launch_fused_combine(const FusedPass& fp, double* w2, int dbuf, Ctl* ctl,
+                                double* hist, SweepParams sp, hipStream_t s);
+int fused_combine_blocks(int64_t rows);
 hipError_t launch_init_exp(const double* w, int64_t len, Ctl* ctl, int idx,
                            hipStream_t s);
 
@@ -196,8 +248,8 @@ hipError_t launch_stable_factors(const void* A, const void* B, ipfp_dtype dt,
 
 // ---- grouped launches (many resident markets per kernel launch) -------------
 
-// One market's half-sweep as the grouped pass, combine and fixup kernels read
-// it: the arguments of the single-market kernels, gathered in device memory.
+// One market's half-sweep as the grouped pass and combine kernels read it
+// (and, passed by value, as the single-market combine reads it).
 struct GroupHalf {
   const uint8_t* Xo;        // output side operands (rows R)
   const float* xscale;
@@ -210,33 +262,23 @@ struct GroupHalf {
   const double* marg;       // R margins
   double* w2;               // output side scaling (double-buffered if dbuf)
   double* res_block;        // combine blocks' residual maxima
-  double* res_slot;         // fixup blocks' residual maxima
-  int32_t* fix_list;
+  double* hist;             // residual history (row pass)
+  SweepParams sp;
   int32_t red_dbuf, exp_red, exp_out, R, L, tiles_per_split, nsplit, dbuf, residual,
       kpad;
 };
-
-// One market's convergence check.
-struct GroupCheck {
-  Ctl* ctl;
-  const double* res_block;
-  double* hist;
-  int32_t nblocks;
-  SweepParams sp;
-};
+GroupHalf fused_half(const FusedPass& fp, Ctl* ctl, double* w2, int dbuf, double* hist,
+                     SweepParams sp);
 
 // Pass over markets idx[0..count) of table g; market idx[j] owns grid blocks
 // [first[j], first[j+1]), first[count] = total. All share kpad and waves.
 hipError_t launch_group_pass(const GroupHalf* g, const int32_t* idx, const int32_t* first,
                              int count, int total, int64_t kpad, ipfp_dtype compute,
                              int tile_rows, hipStream_t s);
-// Combine over markets 0..count of g with block ranges first[] (256 rows each).
+// Combine (with fallback and, for row halves, the check) over markets
+// 0..count of g with block ranges first[] (256 rows each).
 hipError_t launch_group_combine(const GroupHalf* g, const int32_t* first, int count,
-                                int total, hipStream_t s);
-// Fixup with `per` blocks per market.
-hipError_t launch_group_fixup(const GroupHalf* g, int count, int per, ipfp_dtype compute,
-                              hipStream_t s);
-hipError_t launch_group_check(const GroupCheck* c, int count, hipStream_t s);
+                                int total, ipfp_dtype compute, hipStream_t s);
 // Grid size and split bookkeeping of a single-market pass (what the grouped
 // pass must reproduce for bitwise-identical results).
 void fused_pass_grid(const FusedPass& fp, int64_t* blocks, int* tiles_per_split);
@@ -245,6 +287,5 @@ int fused_auto_splits(int64_t R, int64_t L, int rows_per_wg);
 int fused_pass_splits(int64_t R, int64_t L, int64_t kpad, ipfp_dtype compute, int tile_rows);
 int fused_rows_per_wg(int64_t kpad, ipfp_dtype compute, int tile_rows);
 int fused_default_tile_rows(int64_t kpad, ipfp_dtype compute);
-int fused_fixup_blocks();
 
 }  // namespace ipfp

@@ -9,72 +9,10 @@
 
 namespace ipfp {
 
-// One workgroup: reduce the residual maxima of the row pass that just ran
-// (they belong to state i = ctl->sweep), record them at check sweeps, decide
-// whether the solve stops at state i, and otherwise advance to state i + 1.
-// The residual of state i is available here because the row pass of sweep
-// i + 1 computes K v^(i) anyway; u^(i) is kept in the other half of a double
-// buffer, so stopping at i returns exactly (u^(i), v^(i)).
-__device__ __forceinline__ void check_body(Ctl* ctl, const double* res_block, int nblocks,
-                                           double* hist, const SweepParams& sp) {
-  __shared__ double red[256];
-  if (ctl->done) return;
-  const int i = ctl->sweep;
-  const bool chk = is_check(i, sp);
-  double r = 0.0;
-  if (chk) {
-    for (int k = threadIdx.x; k < nblocks; k += blockDim.x) {
-      double x = res_block[k];
-      // NaN compares false: keep it visible
-      r = (x > r || x != x) ? x : r;
-    }
-  }
-  red[threadIdx.x] = r;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      double a = red[threadIdx.x], b = red[threadIdx.x + o];
-      red[threadIdx.x] = (b > a || b != b) ? b : a;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  if (ctl->nonfinite || ctl->bad_margin) {
-    ctl->done = 1;
-    ctl->stop_sweep = i;
-    return;
-  }
-  if (chk) {
-    r = red[0];
-    if (ctl->n_checks < sp.hist_cap) hist[ctl->n_checks] = r;
-    ctl->n_checks += 1;
-    ctl->last_res = r;
-    if (r != r) ctl->nonfinite = 1;
-    if (r < sp.tol || i >= sp.max_sweeps || r != r) {
-      ctl->done = 1;
-      ctl->stop_sweep = i;
-      return;
-    }
-  }
-  ctl->sweep = i + 1;
-}
-
 __global__ void __launch_bounds__(256) k_check(Ctl* ctl, const double* res_block,
                                                int nblocks, double* hist,
                                                SweepParams sp) {
   check_body(ctl, res_block, nblocks, hist, sp);
-}
-
-// One workgroup per market.
-__global__ void __launch_bounds__(256) k_group_check(const GroupCheck* __restrict__ c) {
-  const GroupCheck& g = c[blockIdx.x];
-  check_body(g.ctl, g.res_block, g.nblocks, g.hist, g.sp);
-}
-
-hipError_t launch_group_check(const GroupCheck* c, int count, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_group_check, dim3((unsigned)count), dim3(256), 0, s, c);
-  return hipGetLastError();
 }
 
 hipError_t launch_check(Ctl* ctl, const double* res_block, int nblocks,

@@ -364,10 +364,8 @@ __device__ __forceinline__ void fused_pass_body(
   __shared__ int32_t ysc[2][kTY];          // FP8: E8M0 scale byte per row
 
   if (ctl->done) return;
-  if (!MAXMODE && bid == 0 && threadIdx.x == 0) {
-    ctl->fix_rows = 0;
+  if (!MAXMODE && bid == 0 && threadIdx.x == 0)
     ctl->wexp[exp_out] = INT_MIN;          // the combine of this pass sets it
-  }
   int E = MAXMODE ? 0 : ctl->wexp[exp_red];
   if (E == INT_MIN) E = 0;
   // a double-buffered reduced side (u) holds the current state in the half
@@ -1315,67 +1313,10 @@ __device__ __forceinline__ void block_finish(double res, int ex, double* res_slo
   }
 }
 
-__device__ __forceinline__ void combine_body(
-    const double* __restrict__ part, int splits, int64_t R, const float* __restrict__ shift,
-    int exp_red, int exp_out, const double* __restrict__ marg, double* w2, int dbuf,
-    double* res_block, int32_t* fix_list, int residual, Ctl* ctl, const int bid) {
-  if (ctl->done) return;
-  const int i = ctl->sweep;
-  const double* w_old = dbuf ? w2 + (int64_t)(i & 1) * R : w2;
-  double* w_new = dbuf ? w2 + (int64_t)((i + 1) & 1) * R : w2;
-  int E = ctl->wexp[exp_red];
-  if (E == INT_MIN) E = 0;
-  const int64_t o = (int64_t)bid * 256 + threadIdx.x;
-  double res = 0.0;
-  int ex = INT_MIN;
-  if (o < R) {
-    double l = 0.0;
-    for (int k = 0; k < splits; ++k) l += part[(int64_t)k * R + o];
-    if (!(l >= 0x1p-60) || l == INFINITY) {  // out of the safe range (or NaN)
-      const int slot = atomicAdd(&ctl->fix_rows, 1);
-      fix_list[slot] = (int32_t)o;
-    } else {
-      const double lS = log2(l) + (double)E - (double)shift[o];
-      res = finish_row(o, lS, marg, w_old, w_new, residual != 0, ctl);
-      ex = exponent_of(w_new[o]);
-    }
-  }
-  block_finish(res, ex, &res_block[bid], &ctl->wexp[exp_out]);
-}
-
-__global__ void __launch_bounds__(256)
-    k_fused_combine(const double* __restrict__ part, int splits, int64_t R,
-                    const float* __restrict__ shift, int exp_red, int exp_out,
-                    const double* __restrict__ marg, double* w2, int dbuf,
-                    double* res_block, int32_t* fix_list, int residual, Ctl* ctl) {
-  combine_body(part, splits, R, shift, exp_red, exp_out, marg, w2, dbuf, res_block,
-               fix_list, residual, ctl, (int)blockIdx.x);
-}
-
-__global__ void __launch_bounds__(256)
-    k_group_combine(const GroupHalf* __restrict__ g, const int32_t* __restrict__ first,
-                    int count) {
-  const int j = group_find(first, count, (int)blockIdx.x);
-  const GroupHalf& p = g[j];
-  combine_body(p.part, p.nsplit, p.R, p.shift, p.exp_red, p.exp_out, p.marg, p.w2, p.dbuf,
-               p.res_block, p.fix_list, p.residual, p.ctl,
-               (int)blockIdx.x - __builtin_amdgcn_readfirstlane(first[j]));
-}
-
-// The max pass's combine: h_o = -max over splits.
-__global__ void k_shift_from_max(const double* part, int splits, int64_t R,
-                                 float* shift) {
-  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (o >= R) return;
-  double m = -INFINITY;
-  for (int k = 0; k < splits; ++k) m = fmax(m, part[(int64_t)k * R + o]);
-  shift[o] = (float)(-m);
-}
-
-// Exact fallback for rows whose shifted sum left the safe range: two passes
-// over the reduced side with FP32 dot products of the same packed operands
-// and FP64 log2 weights, the first for the maximum exponent, the second for
-// the sum.
+// Exact fallback for a row whose shifted sum left the safe range: two passes
+// over the reduced side with FP32 dot products of the same packed operands and
+// FP64 log2 weights, the first for the maximum exponent, the second for the
+// sum; the whole workgroup works on one row. Returns log2 (K w)_o.
 template <int OK>
 __device__ __forceinline__ float dot_packed(const uint8_t* a, const uint8_t* b,
                                             int kpad) {
@@ -1397,83 +1338,131 @@ __device__ __forceinline__ float dot_packed(const uint8_t* a, const uint8_t* b,
 }
 
 template <int OK>
-__device__ __forceinline__ void fixup_body(
-    const uint8_t* Xo, const float* xscale, const uint8_t* Yr, const float* yscale, int kpad,
-    const double* wred, int red_dbuf, int exp_out, int64_t L, int64_t R, const double* marg,
-    double* w2, int dbuf, double* res_slot, const int32_t* fix_list, int residual, Ctl* ctl,
-    const int bid, const int nblocks) {
+__device__ __forceinline__ double exact_row_log2(const GroupHalf& p, const double* wred,
+                                                 int64_t o) {
   __shared__ double dred[4];
-  if (ctl->done) return;
-  const int count = ctl->fix_rows;
-  if (bid == 0 && threadIdx.x == 0) ctl->fix_total += count;
-  const int i = ctl->sweep;
-  const double* w_old = dbuf ? w2 + (int64_t)(i & 1) * R : w2;
-  double* w_new = dbuf ? w2 + (int64_t)((i + 1) & 1) * R : w2;
-  if (red_dbuf) wred += (int64_t)(i & 1) * L;
   constexpr bool FP8 = OK == kFP8;
   constexpr int ES = Op<OK>::ES;
-  double res = 0.0;
-  int ex = INT_MIN;
-  for (int k = bid; k < count; k += nblocks) {
-    const int64_t o = fix_list[k];
-    const uint8_t* xr = Xo + o * kpad * ES;
-    const float sx = FP8 ? xscale[o] : 1.f;
-    double tmax = -INFINITY;
-    for (int64_t y = threadIdx.x; y < L; y += 256) {
-      const float sc = FP8 ? sx * yscale[y] : 1.f;
-      const double t = (double)(dot_packed<OK>(xr, Yr + y * kpad * ES, kpad) * sc) +
-                       log2(wred[y]);
-      tmax = fmax(tmax, t);
-    }
-    tmax = wave_max(tmax);
-    if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = tmax;
-    __syncthreads();
-    tmax = fmax(fmax(dred[0], dred[1]), fmax(dred[2], dred[3]));
-    __syncthreads();
-    double sum = 0.0;
-    if (tmax > -INFINITY) {
-      for (int64_t y = threadIdx.x; y < L; y += 256) {
-        const float sc = FP8 ? sx * yscale[y] : 1.f;
-        const double t = (double)(dot_packed<OK>(xr, Yr + y * kpad * ES, kpad) * sc) +
-                         log2(wred[y]);
-        sum += exp2(t - tmax);
-      }
-    }
-    sum = wave_sum(sum);
-    if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = sum;
-    __syncthreads();
-    sum = (dred[0] + dred[1]) + (dred[2] + dred[3]);
-    __syncthreads();
-    const double lS = sum > 0.0 ? tmax + log2(sum) : -INFINITY;
-    if (threadIdx.x == 0) {
-      res = fmax(res, finish_row(o, lS, marg, w_old, w_new, residual != 0, ctl));
-      ex = max(ex, exponent_of(w_new[o]));
+  const int kpad = p.kpad;
+  const uint8_t* xr = p.Xo + o * kpad * ES;
+  const float sx = FP8 ? p.xscale[o] : 1.f;
+  double tmax = -INFINITY;
+  for (int64_t y = threadIdx.x; y < p.L; y += 256) {
+    const float sc = FP8 ? sx * p.yscale[y] : 1.f;
+    const double t =
+        (double)(dot_packed<OK>(xr, p.Yr + y * kpad * ES, kpad) * sc) + log2(wred[y]);
+    tmax = fmax(tmax, t);
+  }
+  tmax = wave_max(tmax);
+  if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = tmax;
+  __syncthreads();
+  tmax = fmax(fmax(dred[0], dred[1]), fmax(dred[2], dred[3]));
+  __syncthreads();
+  double sum = 0.0;
+  if (tmax > -INFINITY) {
+    for (int64_t y = threadIdx.x; y < p.L; y += 256) {
+      const float sc = FP8 ? sx * p.yscale[y] : 1.f;
+      const double t =
+          (double)(dot_packed<OK>(xr, p.Yr + y * kpad * ES, kpad) * sc) + log2(wred[y]);
+      sum += exp2(t - tmax);
     }
   }
-  block_finish(res, ex, &res_slot[bid], &ctl->wexp[exp_out]);
+  sum = wave_sum(sum);
+  if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  sum = (dred[0] + dred[1]) + (dred[2] + dred[3]);
+  __syncthreads();
+  return sum > 0.0 ? tmax + log2(sum) : -INFINITY;
+}
+
+// Combine of one workgroup's 256 output rows: the split partial sums in fixed
+// order (FP64), the residual of the old scaling and the quadratic update of
+// eq. 6; rows whose sum left [2^-60, inf) are recomputed exactly by the whole
+// workgroup (exact_row_log2) before the block's residual and exponent maxima
+// are published. For the row pass (p.residual) the last workgroup to finish
+// (arrival counter in the control block) runs the convergence check, so a
+// sweep needs no separate fallback or check launch.
+template <int OK>
+__device__ __forceinline__ void combine_body(const GroupHalf& p, const int bid,
+                                             const int nblocks) {
+  __shared__ int32_t bad[256];
+  __shared__ int nbad;
+  __shared__ int last;
+  Ctl* ctl = p.ctl;
+  if (ctl->done) return;
+  const int64_t R = p.R;
+  const int i = ctl->sweep;
+  const double* w_old = p.dbuf ? p.w2 + (int64_t)(i & 1) * R : p.w2;
+  double* w_new = p.dbuf ? p.w2 + (int64_t)((i + 1) & 1) * R : p.w2;
+  int E = ctl->wexp[p.exp_red];
+  if (E == INT_MIN) E = 0;
+  if (threadIdx.x == 0) nbad = 0;
+  __syncthreads();
+  const int64_t o = (int64_t)bid * 256 + threadIdx.x;
+  double res = 0.0;
+  int ex = INT_MIN;
+  if (o < R) {
+    double l = 0.0;
+    for (int k = 0; k < p.nsplit; ++k) l += p.part[(int64_t)k * R + o];
+    if (!(l >= 0x1p-60) || l == INFINITY) {  // out of the safe range (or NaN)
+      bad[atomicAdd(&nbad, 1)] = (int32_t)threadIdx.x;
+    } else {
+      const double lS = log2(l) + (double)E - (double)p.shift[o];
+      res = finish_row(o, lS, p.marg, w_old, w_new, p.residual != 0, ctl);
+      ex = exponent_of(w_new[o]);
+    }
+  }
+  __syncthreads();
+  const int nb = nbad;
+  if (nb > 0) {
+    const double* wred = p.red_dbuf ? p.wred + (int64_t)(i & 1) * p.L : p.wred;
+    for (int k = 0; k < nb; ++k) {
+      const int t = bad[k];
+      const int64_t ob = (int64_t)bid * 256 + t;
+      const double lS = exact_row_log2<OK>(p, wred, ob);
+      if (threadIdx.x == t) {
+        res = finish_row(ob, lS, p.marg, w_old, w_new, p.residual != 0, ctl);
+        ex = exponent_of(w_new[ob]);
+      }
+    }
+    if (threadIdx.x == 0) atomicAdd(&ctl->fix_total, nb);
+  }
+  block_finish(res, ex, &p.res_block[bid], &ctl->wexp[p.exp_out]);
+  if (!p.residual) return;
+  // arrival: this block's residual (and any flag it raised) is visible before
+  // the counter moves; the last block resets the counter and runs the check
+  __threadfence();
+  if (threadIdx.x == 0) last = atomicAdd(&ctl->arrive, 1) == nblocks - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x == 0) ctl->arrive = 0;
+  check_body(ctl, p.res_block, nblocks, p.hist, p.sp);
+}
+
+template <int OK>
+__global__ void __launch_bounds__(256) k_fused_combine(GroupHalf p) {
+  combine_body<OK>(p, (int)blockIdx.x, (int)gridDim.x);
 }
 
 template <int OK>
 __global__ void __launch_bounds__(256)
-    k_fused_fixup(const uint8_t* Xo, const float* xscale, const uint8_t* Yr,
-                  const float* yscale, int kpad, const double* wred, int red_dbuf,
-                  int exp_out, int64_t L, int64_t R, const double* marg, double* w2, int dbuf,
-                  double* res_slot, const int32_t* fix_list, int residual,
-                  Ctl* ctl) {
-  fixup_body<OK>(Xo, xscale, Yr, yscale, kpad, wred, red_dbuf, exp_out, L, R, marg, w2,
-                  dbuf, res_slot, fix_list, residual, ctl, (int)blockIdx.x,
-                  (int)gridDim.x);
+    k_group_combine(const GroupHalf* __restrict__ g, const int32_t* __restrict__ first,
+                    int count) {
+  const int j = group_find(first, count, (int)blockIdx.x);
+  const int b0 = __builtin_amdgcn_readfirstlane(first[j]);
+  const int b1 = __builtin_amdgcn_readfirstlane(first[j + 1]);
+  combine_body<OK>(g[j], (int)blockIdx.x - b0, b1 - b0);
 }
 
-// Grouped fixup: `per` blocks per market, market j owns blocks [j per, (j+1) per).
-template <int OK>
-__global__ void __launch_bounds__(256)
-    k_group_fixup(const GroupHalf* __restrict__ g, int per) {
-  const int j = (int)blockIdx.x / per;
-  const GroupHalf& p = g[j];
-  fixup_body<OK>(p.Xo, p.xscale, p.Yr, p.yscale, p.kpad, p.wred, p.red_dbuf, p.exp_out,
-                  p.L, p.R, p.marg, p.w2, p.dbuf, p.res_slot, p.fix_list, p.residual, p.ctl,
-                  (int)blockIdx.x - j * per, per);
+// The max pass's combine: h_o = -max over splits.
+__global__ void k_shift_from_max(const double* part, int splits, int64_t R,
+                                 float* shift) {
+  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (o >= R) return;
+  double m = -INFINITY;
+  for (int k = 0; k < splits; ++k) m = fmax(m, part[(int64_t)k * R + o]);
+  shift[o] = (float)(-m);
 }
 
 // ctl->wexp[idx] = largest binary exponent of w (one workgroup).
@@ -1578,33 +1567,49 @@ int fused_rows_per_wg(int64_t kpad, ipfp_dtype compute, int tile_rows) {
   return pass_waves(ok, xt, tile_rows) * xt * 32;
 }
 
-hipError_t launch_fused_combine(const FusedPass& fp, double* w2, int dbuf,
-                                Ctl* ctl, int* nblocks, hipStream_t s) {
-  const int64_t blocks = (fp.out.rows + 255) / 256;
-  *nblocks = (int)blocks;
-  hipLaunchKernelGGL(k_fused_combine, dim3((unsigned)blocks), dim3(256), 0, s,
-                     fp.part, fp.splits, fp.out.rows, fp.shift, fp.exp_red,
-                     fp.exp_out, fp.marg, w2, dbuf, fp.res_block, fp.fix_list,
-                     fp.residual ? 1 : 0, ctl);
-  return hipGetLastError();
+GroupHalf fused_half(const FusedPass& fp, Ctl* ctl, double* w2, int dbuf, double* hist,
+                     SweepParams sp) {
+  GroupHalf g{};
+  g.Xo = (const uint8_t*)fp.out.ops;
+  g.xscale = fp.out.scale;
+  g.Yr = (const uint8_t*)fp.red.ops;
+  g.yscale = fp.red.scale;
+  g.wred = fp.w_red;
+  g.shift = fp.shift;
+  g.part = fp.part;
+  g.ctl = ctl;
+  g.marg = fp.marg;
+  g.w2 = w2;
+  g.res_block = fp.res_block;
+  g.hist = hist;
+  g.sp = sp;
+  g.red_dbuf = fp.red_dbuf;
+  g.exp_red = fp.exp_red;
+  g.exp_out = fp.exp_out;
+  g.R = (int32_t)fp.out.rows;
+  g.L = (int32_t)fp.red.rows;
+  int64_t blocks = 0;
+  int tps = 0;
+  fused_pass_grid(fp, &blocks, &tps);
+  g.tiles_per_split = tps;
+  g.nsplit = fp.splits;
+  g.dbuf = dbuf;
+  g.residual = fp.residual ? 1 : 0;
+  g.kpad = (int32_t)fp.kpad;
+  return g;
 }
 
-constexpr int kFixupBlocks = 64;
-int fused_fixup_blocks() { return kFixupBlocks; }
+int fused_combine_blocks(int64_t rows) { return (int)((rows + 255) / 256); }
 
-hipError_t launch_fused_fixup(const FusedPass& fp, double* w2, int dbuf,
-                              double* res_slot, Ctl* ctl, hipStream_t s) {
-#define IPFP_FIXUP_ARGS                                                                     \
-  dim3(kFixupBlocks), dim3(256), 0, s, (const uint8_t*)fp.out.ops, fp.out.scale,           \
-      (const uint8_t*)fp.red.ops, fp.red.scale, (int)fp.kpad, fp.w_red, fp.red_dbuf,        \
-      fp.exp_out, fp.red.rows, fp.out.rows, fp.marg, w2, dbuf, res_slot, fp.fix_list,      \
-      fp.residual ? 1 : 0, ctl
+hipError_t launch_fused_combine(const FusedPass& fp, double* w2, int dbuf, Ctl* ctl,
+                                double* hist, SweepParams sp, hipStream_t s) {
+  const GroupHalf g = fused_half(fp, ctl, w2, dbuf, hist, sp);
+  const dim3 grid((unsigned)fused_combine_blocks(fp.out.rows));
   switch (op_kind(fp.compute)) {
-    case kFP8: hipLaunchKernelGGL(k_fused_fixup<kFP8>, IPFP_FIXUP_ARGS); break;
-    case kF32: hipLaunchKernelGGL(k_fused_fixup<kF32>, IPFP_FIXUP_ARGS); break;
-    default: hipLaunchKernelGGL(k_fused_fixup<kBF16>, IPFP_FIXUP_ARGS); break;
+    case kFP8: hipLaunchKernelGGL(k_fused_combine<kFP8>, grid, dim3(256), 0, s, g); break;
+    case kF32: hipLaunchKernelGGL(k_fused_combine<kF32>, grid, dim3(256), 0, s, g); break;
+    default: hipLaunchKernelGGL(k_fused_combine<kBF16>, grid, dim3(256), 0, s, g); break;
   }
-#undef IPFP_FIXUP_ARGS
   return hipGetLastError();
 }
 
@@ -1656,21 +1661,14 @@ hipError_t launch_group_pass(const GroupHalf* g, const int32_t* idx, const int32
 }
 
 hipError_t launch_group_combine(const GroupHalf* g, const int32_t* first, int count,
-                                int total, hipStream_t s) {
+                                int total, ipfp_dtype compute, hipStream_t s) {
   if (count <= 0 || total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_group_combine, dim3((unsigned)total), dim3(256), 0, s, g, first,
-                     count);
-  return hipGetLastError();
-}
-
-hipError_t launch_group_fixup(const GroupHalf* g, int count, int per, ipfp_dtype compute,
-                              hipStream_t s) {
-  if (count <= 0 || per <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)(count * per);
   if (compute == IPFP_FP8E4M3)
-    hipLaunchKernelGGL(k_group_fixup<kFP8>, dim3(grid), dim3(256), 0, s, g, per);
+    hipLaunchKernelGGL(k_group_combine<kFP8>, dim3((unsigned)total), dim3(256), 0, s, g, first,
+                       count);
   else
-    hipLaunchKernelGGL(k_group_fixup<kBF16>, dim3(grid), dim3(256), 0, s, g, per);
+    hipLaunchKernelGGL(k_group_combine<kBF16>, dim3((unsigned)total), dim3(256), 0, s, g, first,
+                       count);
   return hipGetLastError();
 }
 

@@ -85,7 +85,6 @@ struct ipfp_handle {
   float *xscale = nullptr, *yscale = nullptr;
   float *xshift = nullptr, *yshift = nullptr;
   double *xpart = nullptr, *ypart = nullptr;
-  int32_t *xfix = nullptr, *yfix = nullptr;
   ipfp::FusedPass rowp{}, colp{};
   int row_combine_blocks = 0, col_combine_blocks = 0;
   // loop state

@@ -93,13 +93,11 @@ void ipfp::handle_layout(ipfp_handle* h, Carver& cv) {
     int sy = scol > 0 ? scol : fused_pass_splits(M, N, h->kpad, cd, tr);
     h->xpart = cv.take<double>((size_t)sx * N);
     h->ypart = cv.take<double>((size_t)sy * M);
-    h->xfix = cv.take<int32_t>(N);
-    h->yfix = cv.take<int32_t>(M);
-    h->row_combine_blocks = (int)((N + 255) / 256);
-    h->col_combine_blocks = (int)((M + 255) / 256);
-    h->nres_row = h->row_combine_blocks + fused_fixup_blocks();
+    h->row_combine_blocks = fused_combine_blocks(N);
+    h->col_combine_blocks = fused_combine_blocks(M);
+    h->nres_row = h->row_combine_blocks;
     h->res_block = cv.take<double>(h->nres_row);
-    h->res_dummy = cv.take<double>(h->col_combine_blocks + fused_fixup_blocks());
+    h->res_dummy = cv.take<double>(h->col_combine_blocks);
     h->rowp.splits = sx;
     h->colp.splits = sy;
     h->rowp.tile_rows = h->colp.tile_rows = tr;
@@ -192,21 +190,15 @@ static hipError_t enqueue_unit(ipfp_handle* h, hipStream_t s, bool timing) {
                               h->mk.m, h->v, h->ctl, s);
     });
   }
+  // fused: four launches per sweep -- each combine also runs the exact
+  // fallback for its rows, the row combine's last workgroup the check
   e = timed(h, timing, s, [&] { return launch_fused_pass(h->rowp, h->ctl, s); });
   if (e != hipSuccess) return e;
-  e = launch_fused_combine(h->rowp, h->u2, 1, h->ctl, &nb, s);
-  if (e != hipSuccess) return e;
-  e = launch_fused_fixup(h->rowp, h->u2, 1, h->res_block + h->row_combine_blocks,
-                         h->ctl, s);
-  if (e != hipSuccess) return e;
-  e = launch_check(h->ctl, h->res_block, h->nres_row, h->hist, sp, s);
+  e = launch_fused_combine(h->rowp, h->u2, 1, h->ctl, h->hist, sp, s);
   if (e != hipSuccess) return e;
   e = timed(h, timing, s, [&] { return launch_fused_pass(h->colp, h->ctl, s); });
   if (e != hipSuccess) return e;
-  e = launch_fused_combine(h->colp, h->v, 0, h->ctl, &nb, s);
-  if (e != hipSuccess) return e;
-  return launch_fused_fixup(h->colp, h->v, 0,
-                            h->res_dummy + h->col_combine_blocks, h->ctl, s);
+  return launch_fused_combine(h->colp, h->v, 0, h->ctl, h->hist, sp, s);
 }
 
 static int read_ctl(ipfp_handle* h, hipStream_t s) {
@@ -279,13 +271,13 @@ hipError_t ipfp::handle_setup(ipfp_handle* h, const void* phi, ipfp_dtype phi_dt
   r.out = X; r.red = Y; r.compute = cd; r.kpad = h->kpad;
   r.w_red = h->v; r.red_dbuf = 0; r.exp_red = 1; r.exp_out = 0;
   r.shift = h->xshift; r.marg = mk->n;
-  r.part = h->xpart; r.res_block = h->res_block; r.fix_list = h->xfix;
+  r.part = h->xpart; r.res_block = h->res_block;
   r.residual = true;
   FusedPass& q = h->colp;
   q.out = Y; q.red = X; q.compute = cd; q.kpad = h->kpad;
   q.w_red = h->u2; q.red_dbuf = 1; q.exp_red = 0; q.exp_out = 1;
   q.shift = h->yshift; q.marg = mk->m;
-  q.part = h->ypart; q.res_block = h->res_dummy; q.fix_list = h->yfix;
+  q.part = h->ypart; q.res_block = h->res_dummy;
   q.residual = false;
   // fixed row shifts h = -max T from one max pass per side; exponent of v0
   TRY(launch_fused_shift(r, h->ctl, s));

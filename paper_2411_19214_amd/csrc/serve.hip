@@ -8,9 +8,10 @@
 // than a fill target: a lane that already fills the chip gains nothing from
 // another market but would share its time with it. Admission packs the market
 // on its lane's stream. Each lane runs rounds: a round is `chunk` sweeps over all markets
-// resident on the lane, each sweep being seven grouped launches (row pass,
-// combine, fixup, convergence check, column pass, combine, fixup) whose grids
-// concatenate the markets' single-market grids, followed by one copy of the
+// resident on the lane, each sweep being four grouped launches (row pass, row
+// combine with the exact fallback and each market's convergence check, column
+// pass, column combine) whose grids concatenate the markets' single-market
+// grids, followed by one copy of the
 // control blocks to the host. After a round the scheduler retires the markets
 // whose device loop has stopped (copying a, b and the residual history out)
 // and lets newly admitted markets join. Lanes run concurrently, so small
@@ -33,7 +34,6 @@ using namespace ipfp;
 namespace {
 
 constexpr int kMaxLanes = 4;
-constexpr int kGroupFixupBlocks = 16;   // fixup workgroups per market
 
 // First-fit allocator over [0, cap) with coalescing; 256-byte granules.
 class Arena {
@@ -136,7 +136,6 @@ struct Lane {
   Ctl* hctl = nullptr;      // pinned mirror of the control-block pool
   // device addresses inside dtab of the current table
   const GroupHalf *row = nullptr, *col = nullptr;
-  const GroupCheck* chk = nullptr;
   const int32_t *row_idx = nullptr, *col_idx = nullptr;
   const int32_t *row_pf = nullptr, *col_pf = nullptr;
   const int32_t *row_cf = nullptr, *col_cf = nullptr;
@@ -175,11 +174,11 @@ struct ipfp_server {
 namespace {
 
 // Offsets of the grouped-launch table of `count` markets with `nk` distinct
-// kpads: two GroupHalf arrays, the checks, then int32 arrays -- pass market
-// indices (row, column), pass block starts (count + nk each), combine block
-// starts (count + 1 each).
+// kpads: two GroupHalf arrays, then int32 arrays -- pass market indices (row,
+// column), pass block starts (count + nk each), combine block starts (count +
+// 1 each).
 struct TableLayout {
-  size_t row, col, chk, ridx, cidx, rpf, cpf, rcf, ccf, total;
+  size_t row, col, ridx, cidx, rpf, cpf, rcf, ccf, total;
 };
 
 TableLayout table_layout(int count, int nk) {
@@ -193,7 +192,6 @@ TableLayout table_layout(int count, int nk) {
   };
   t.row = take(sizeof(GroupHalf) * count);
   t.col = take(sizeof(GroupHalf) * count);
-  t.chk = take(sizeof(GroupCheck) * count);
   t.ridx = take(sizeof(int32_t) * count);
   t.cidx = take(sizeof(int32_t) * count);
   t.rpf = take(sizeof(int32_t) * (count + nk));
@@ -212,35 +210,8 @@ int lane_for(const ipfp_server* srv, int64_t N, int64_t M) {
 }
 
 GroupHalf half_of(const ipfp_handle* h, bool row) {
-  const FusedPass& fp = row ? h->rowp : h->colp;
-  GroupHalf g{};
-  g.Xo = (const uint8_t*)fp.out.ops;
-  g.xscale = fp.out.scale;
-  g.Yr = (const uint8_t*)fp.red.ops;
-  g.yscale = fp.red.scale;
-  g.wred = fp.w_red;
-  g.shift = fp.shift;
-  g.part = fp.part;
-  g.ctl = h->ctl;
-  g.marg = fp.marg;
-  g.w2 = row ? h->u2 : h->v;
-  g.res_block = fp.res_block;
-  g.res_slot = fp.res_block + (row ? h->row_combine_blocks : h->col_combine_blocks);
-  g.fix_list = fp.fix_list;
-  g.red_dbuf = fp.red_dbuf;
-  g.exp_red = fp.exp_red;
-  g.exp_out = fp.exp_out;
-  g.R = (int32_t)fp.out.rows;
-  g.L = (int32_t)fp.red.rows;
-  int64_t blocks = 0;
-  int tps = 0;
-  fused_pass_grid(fp, &blocks, &tps);
-  g.tiles_per_split = tps;
-  g.nsplit = fp.splits;
-  g.dbuf = row ? 1 : 0;
-  g.residual = fp.residual ? 1 : 0;
-  g.kpad = (int32_t)fp.kpad;
-  return g;
+  return fused_half(row ? h->rowp : h->colp, h->ctl, row ? h->u2 : h->v, row ? 1 : 0, h->hist,
+                    handle_sweep_params(h));
 }
 
 int64_t pass_blocks(const FusedPass& fp) {
@@ -284,13 +255,11 @@ hipError_t build_table(Lane& L) {
     if (e != hipSuccess) return e;
     L.tab_cap = cap;
   }
-  const size_t o_row = t.row, o_col = t.col, o_chk = t.chk, o_ridx = t.ridx,
-               o_cidx = t.cidx, o_rpf = t.rpf, o_cpf = t.cpf, o_rcf = t.rcf, o_ccf = t.ccf,
-               used = t.total;
+  const size_t o_row = t.row, o_col = t.col, o_ridx = t.ridx, o_cidx = t.cidx,
+               o_rpf = t.rpf, o_cpf = t.cpf, o_rcf = t.rcf, o_ccf = t.ccf, used = t.total;
 
   GroupHalf* row = (GroupHalf*)(L.htab + o_row);
   GroupHalf* col = (GroupHalf*)(L.htab + o_col);
-  GroupCheck* chk = (GroupCheck*)(L.htab + o_chk);
   int32_t* ridx = (int32_t*)(L.htab + o_ridx);
   int32_t* cidx = (int32_t*)(L.htab + o_cidx);
   int32_t* rpf = (int32_t*)(L.htab + o_rpf);
@@ -311,12 +280,6 @@ hipError_t build_table(Lane& L) {
     const ipfp_handle* h = L.active[j]->h;
     row[j] = half_of(h, true);
     col[j] = half_of(h, false);
-    GroupCheck& c = chk[j];
-    c.ctl = h->ctl;
-    c.res_block = h->res_block;
-    c.hist = h->hist;
-    c.nblocks = h->row_combine_blocks + kGroupFixupBlocks;
-    c.sp = handle_sweep_params(h);
     PassKey& pk = L.keys[key_of[j]];
     ridx[pk.idx_off + pk.cnt] = j;
     cidx[pk.idx_off + pk.cnt] = j;
@@ -340,7 +303,6 @@ hipError_t build_table(Lane& L) {
   L.col_ctot = cc_acc;
   L.row = (const GroupHalf*)(L.dtab + o_row);
   L.col = (const GroupHalf*)(L.dtab + o_col);
-  L.chk = (const GroupCheck*)(L.dtab + o_chk);
   L.row_idx = (const int32_t*)(L.dtab + o_ridx);
   L.col_idx = (const int32_t*)(L.dtab + o_cidx);
   L.row_pf = (const int32_t*)(L.dtab + o_rpf);
@@ -366,14 +328,11 @@ hipError_t enqueue_group_unit(ipfp_server* srv, Lane& L) {
   for (const PassKey& k : L.keys)
     TRY(launch_group_pass(L.row, L.row_idx + k.idx_off, L.row_pf + k.first_off, k.cnt,
                           k.row_total, k.kpad, cd, tr(k.kpad), L.s));
-  TRY(launch_group_combine(L.row, L.row_cf, count, L.row_ctot, L.s));
-  TRY(launch_group_fixup(L.row, count, kGroupFixupBlocks, cd, L.s));
-  TRY(launch_group_check(L.chk, count, L.s));
+  TRY(launch_group_combine(L.row, L.row_cf, count, L.row_ctot, cd, L.s));
   for (const PassKey& k : L.keys)
     TRY(launch_group_pass(L.col, L.col_idx + k.idx_off, L.col_pf + k.first_off, k.cnt,
                           k.col_total, k.kpad, cd, tr(k.kpad), L.s));
-  TRY(launch_group_combine(L.col, L.col_cf, count, L.col_ctot, L.s));
-  return launch_group_fixup(L.col, count, kGroupFixupBlocks, cd, L.s);
+  return launch_group_combine(L.col, L.col_cf, count, L.col_ctot, cd, L.s);
 }
 
 hipError_t start_round(ipfp_server* srv, Lane& L) {
