@@ -431,6 +431,18 @@ def run_pass(torch, L, spec, steps, warmup):
             "pair_evals_per_s": 2.0 * mk.N * mk.M * steps / (r["ms"] / 1e3)}
 
 
+def run_tune_serving(torch, L, count=128, repeats=3):
+    """Serving widths (sweeps per round, lane fill target, lanes) tuned on the
+    first `count` requests of the serving mix, each candidate run `repeats`
+    times (paper_2411_19214_amd.tune.tune_serving)."""
+    from paper_2411_19214_amd import tune
+    reqs = workloads.serving_requests()[:count]
+    tens = [workloads.device_request_factors(torch, r) for r in reqs]
+    torch.cuda.synchronize()
+    return tune.tune_serving(tens, [r.arrival_s for r in reqs], [r.sigma for r in reqs],
+                             repeats=repeats, log=log)
+
+
 def run_probes(torch, L):
     """The roofline probes (ipfp_probe): exp2 results/s, dense MFMA flop/s of
     the BF16, FP8 and FP32 instructions the fused passes use, and the
@@ -489,6 +501,8 @@ def main():
                          "at this sigma (FP32 reference vs BF16 and FP8, 200 sweeps)")
     ap.add_argument("--probes", action="store_true",
                     help="run only the roofline probes (exp2, MFMA, HBM read)")
+    ap.add_argument("--tune-serving", action="store_true",
+                    help="run only the serving-width tuner on the first 128 requests")
     ap.add_argument("--pass", dest="pass_spec", default=None, metavar="CFG:TYPE[:SIGMA]",
                     help="run only one configuration's fused pass, e.g. c5:fp8 (profiling)")
     ap.add_argument("--max-sweeps", type=int, default=200,
@@ -524,6 +538,9 @@ def main():
         return
     if args.probes:
         print(json.dumps({"probes": run_probes(torch, L)}), flush=True)
+        return
+    if args.tune_serving:
+        print(json.dumps({"tune_serving": run_tune_serving(torch, L)}), flush=True)
         return
     if args.pass_spec:
         print(json.dumps({"pass": run_pass(torch, L, args.pass_spec, args.steps, args.warmup)}),

@@ -1002,6 +1002,14 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Stages of FP32 product accumulation between folds into the FP64 sums: each
+// FP32 accumulator takes kTY / 8 MFMA additions per stage (16 at kTY = 128,
+// high and low parts), so a fold every F stages bounds its rounding at about
+// 16 F x 2^-24 of the folded terms' magnitudes.
+#ifndef IPFP_GRAD_FOLD
+#define IPFP_GRAD_FOLD 4
+#endif
+
 // 32-column blocks of G per workgroup, and waves per workgroup
 constexpr int grad_col_blocks(int kp) { return kp / 32 < 4 ? kp / 32 : 4; }
 constexpr int kGradWaves = 4;
@@ -1173,14 +1181,18 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
         }
       }
     }
-    // lane (o, h) holds columns 32 (nb0 + nb) + 8 (j / 4) + 4 h + j % 4 of row o
+    // lane (o, h) holds columns 32 (nb0 + nb) + 8 (j / 4) + 4 h + j % 4 of row o;
+    // the FP32 products are folded into the FP64 sums every IPFP_GRAD_FOLD
+    // stages (and after the last)
+    if ((tile - t0) % IPFP_GRAD_FOLD == IPFP_GRAD_FOLD - 1 || tile == t1 - 1) {
 #pragma unroll
-    for (int nb = 0; nb < NBL; ++nb)
+      for (int nb = 0; nb < NBL; ++nb)
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        g64[nb][j] += (double)g32[nb][j];
-        g32[nb][j] = 0.f;
-      }
+        for (int j = 0; j < 16; ++j) {
+          g64[nb][j] += (double)g32[nb][j];
+          g32[nb][j] = 0.f;
+        }
+    }
     lstore(buf ^ 1);
     __syncthreads();
   }

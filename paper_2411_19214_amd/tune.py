@@ -97,3 +97,84 @@ def tuned(U, Q, V, P, n, m, sigma, compute="bf16", path=None, refresh=False,
                   "tuned_shape": [N, M, d], "splits": [best.splits, best.splits_col]}
     _store(path, table)
     return _apply(choice, N, M, d, compute)
+
+
+# --- serving widths ----------------------------------------------------------
+
+SERVING_CANDIDATES = {"chunk": (2, 4, 8), "lane_blocks": (1024, 2048, 4096), "lanes": (2, 3, 4)}
+
+
+def serving_key(arch: str, compute: str) -> str:
+    return f"serving|{arch}|{compute}"
+
+
+def _run_mix(markets, arrivals, sigmas, compute, tol, max_sweeps, **server_opts):
+    """One pass of a request mix through a fresh server; (p50, p99) of the
+    sojourn time (ms) and the makespan (ms)."""
+    import time
+
+    import numpy as np
+
+    from . import Server, clock_ms
+    with Server(compute=compute, **server_opts) as srv:
+        reqs = []
+        t0 = clock_ms()
+        for t, at, sg in zip(markets, arrivals, sigmas):
+            due = t0 + 1e3 * at
+            while clock_ms() < due:
+                time.sleep(min(0.002, max(0.0, (due - clock_ms()) / 1e3)))
+            reqs.append(srv.submit(*t, sg, tol=tol, max_sweeps=max_sweeps))
+        for r in reqs:
+            srv.wait(r)
+    soj = np.array([r.t_done - r.t_submit for r in reqs])
+    return (float(np.percentile(soj, 50)), float(np.percentile(soj, 99)),
+            max(r.t_done for r in reqs) - t0)
+
+
+def tune_serving(markets, arrivals, sigmas, compute="bf16", tol=1e-6, max_sweeps=200,
+                 repeats=3, arena_bytes=16 << 30, path=None, log=None) -> dict:
+    """Serving widths for a request mix: coordinate search over the server's
+    sweeps per round (chunk), lane fill target (lane_blocks) and number of
+    lanes, each candidate run `repeats` times on the same mix (markets: list of
+    (U, Q, V, P, n, m) device tensors; arrivals in seconds from the first;
+    sigmas). The score is the median over repeats of the p99 sojourn time.
+    The winner is cached in the tuning JSON under the device's serving key."""
+    import statistics
+
+    import torch
+    best = {"chunk": 4, "lane_blocks": 2048, "lanes": 3}
+    trials = []
+
+    def score(opts):
+        runs = [_run_mix(markets, arrivals, sigmas, compute, tol, max_sweeps,
+                         arena_bytes=arena_bytes, **opts) for _ in range(repeats)]
+        p99 = statistics.median(r[1] for r in runs)
+        trials.append({"options": dict(opts), "p50_ms": [r[0] for r in runs],
+                       "p99_ms": [r[1] for r in runs], "makespan_ms": [r[2] for r in runs]})
+        if log:
+            log(f"serving tune {opts}: p99 {p99:.1f} ms")
+        return p99
+
+    best_s = score(best)
+    for knob, values in SERVING_CANDIDATES.items():
+        start = best[knob]
+        for v in values:
+            if v == start:
+                continue
+            cand = dict(best, **{knob: v})
+            sc = score(cand)
+            if sc < best_s:
+                best, best_s = cand, sc
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path = path or cache_path()
+    table = _load(path)
+    table[serving_key(arch, compute)] = {"choice": best, "p99_ms": best_s, "trials": trials}
+    _store(path, table)
+    return {"choice": best, "p99_ms": best_s, "trials": trials}
+
+
+def tuned_serving(compute="bf16", path=None) -> dict:
+    """The cached serving widths for this device (empty when never tuned)."""
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    return dict(_load(path or cache_path()).get(serving_key(arch, compute), {}).get("choice", {}))

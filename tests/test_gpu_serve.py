@@ -49,12 +49,15 @@ def alone(torch, lib, t, spec, compute):
                             compute=compute)
 
 
-@pytest.mark.parametrize("compute", ["bf16", "fp8"])
-def test_mix_equals_alone_bitwise(torch, lib, compute):
-    banner(f"serve mix vs alone {compute}")
+@pytest.mark.parametrize("compute,widths", [
+    ("bf16", dict(chunk=3, lanes=3)), ("fp8", dict(chunk=3, lanes=3)),
+    ("bf16", dict(chunk=1, lanes=4, lane_blocks=512)),
+    ("bf16", dict(chunk=8, lanes=2, lane_blocks=4096))])
+def test_mix_equals_alone_bitwise(torch, lib, compute, widths):
+    banner(f"serve mix vs alone {compute} {widths}")
     mks = [mix_market(i, *s[:4]) for i, s in enumerate(MIX)]
     tens = [market_tensors(torch, mk) for mk in mks]
-    with lib.Server(compute=compute, chunk=3, lanes=3) as srv:
+    with lib.Server(compute=compute, **widths) as srv:
         reqs = []
         # half now, the rest while the first half runs
         for i, (t, s) in enumerate(zip(tens, MIX)):
@@ -67,7 +70,8 @@ def test_mix_equals_alone_bitwise(torch, lib, compute):
         lanes = {r.lane for r in reqs}
         st = srv.stats()
     assert all(r.finished for r in reqs)
-    assert len(lanes) == 3, lanes
+    # the mix's sizes fall in three size classes whatever the lane count
+    assert len(lanes) == min(widths["lanes"], 3), lanes
     assert st["finished"] == len(MIX) and st["arena_used"] == 0
     for t, s, r in zip(tens, MIX, reqs):
         a, b, info = alone(torch, lib, t, s, compute)
@@ -75,6 +79,31 @@ def test_mix_equals_alone_bitwise(torch, lib, compute):
         assert r.info.sweeps == info.sweeps and r.info.residuals == info.residuals, s
         assert torch.equal(r.a, a) and torch.equal(r.b, b), s
         assert r.t_submit <= r.t_admit <= r.t_done
+
+
+def test_serving_tuner_choice_keeps_results(torch, lib, tmp_path):
+    """The serving-width tuner runs a small mix over its candidates and caches
+    a choice; a server with those widths still returns every request's
+    alone-solve result bit for bit."""
+    from paper_2411_19214_amd import tune
+    banner("serving tuner on a small mix")
+    specs = MIX[:5]
+    mks = [mix_market(i, *s[:4]) for i, s in enumerate(specs)]
+    tens = [market_tensors(torch, mk) for mk in mks]
+    path = str(tmp_path / "tune.json")
+    out = tune.tune_serving(tens, [0.0, 0.001, 0.002, 0.003, 0.004], [s[3] for s in specs],
+                            repeats=1, arena_bytes=1 << 30, path=path, max_sweeps=40)
+    choice = out["choice"]
+    assert len(out["trials"]) == 7
+    assert set(choice) == {"chunk", "lane_blocks", "lanes"}
+    assert tune._load(path)
+    with lib.Server(compute="bf16", **choice) as srv:
+        reqs = [srv.submit(*t, s[3], tol=1e-6, max_sweeps=40) for t, s in zip(tens, specs)]
+        for r in reqs:
+            srv.wait(r, timeout_ms=60_000)
+    for t, s, r in zip(tens, specs, reqs):
+        a, b, info = lib.solve_market(*t, s[3], tol=1e-6, max_sweeps=40)
+        assert r.status == info.status and torch.equal(r.a, a) and torch.equal(r.b, b)
 
 
 def test_unconverged_mix_shapes_follow_the_oracle(torch, lib):
