@@ -972,7 +972,7 @@ hipError_t launch_topk(const FusedPass& fp, const double* a_out, int k, int spli
 // the B operand. A workgroup (4 waves, one per SIMD: the FP64 sums take the
 // registers of a second) covers 128 output rows and up to four 32-column
 // blocks of G; wider rows take two column groups, each recomputing T. FP32
-// accumulators are folded into FP64 registers after every stage; one FP64
+// accumulators are folded into FP64 registers every IPFP_GRAD_FOLD stages; one FP64
 // partial per (split, row, column) results.
 
 // Column-major copy of the packed reduced side: Yt[c][y] = Yr[y][c] for
@@ -1010,24 +1010,29 @@ __global__ void __launch_bounds__(256)
 #define IPFP_GRAD_FOLD 4
 #endif
 
-// 32-column blocks of G per workgroup, and waves per workgroup
+// 32-column blocks of G per workgroup (at most), and waves per workgroup
 constexpr int grad_col_blocks(int kp) { return kp / 32 < 4 ? kp / 32 : 4; }
 constexpr int kGradWaves = 4;
 
-template <int KP>
+// NBL 32-column blocks per workgroup, a compile-time count: the product loop
+// then has no branches, and its LDS reads and MFMAs schedule as one block.
+// Groups g = 0 .. ngroups-1 cover column blocks nb_base + NBL g onwards; a
+// row of 2d columns that is not a multiple of 4 blocks takes a second launch
+// for its last, narrower group.
+template <int KP, int NBL>
 __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
     k_grad_pass(const uint8_t* __restrict__ Xo, const uint8_t* __restrict__ Yr,
                 const uint16_t* __restrict__ Yt, int Lp, const double* __restrict__ wred,
                 const int* __restrict__ Eptr, const float* __restrict__ shift, int R, int L,
-                int tiles_per_split, int nsplit, int ngroups, double* __restrict__ gpart) {
+                int tiles_per_split, int nsplit, int ngroups, int nb_base,
+                double* __restrict__ gpart) {
   constexpr int WAVES = kGradWaves;
   typedef PassCore<KP, 1, WAVES, kBF16> C;
   typedef typename C::Frag Frag;
   typedef Op<kBF16> O;
   constexpr int RB = C::RB, kTY = C::kTY, NS = C::NS, LS = C::LS, NT = C::NT;
   constexpr int CH = C::CH, CPT = C::CPT, SUB = C::SUB;
-  constexpr int NB = KP / 32;               // 32-column blocks of the value rows
-  constexpr int NBL = grad_col_blocks(KP);  // ... handled by one workgroup
+  static_assert(NBL >= 1 && NBL <= 4 && NBL <= KP / 32, "column blocks per workgroup");
   // bytes per staged column. A column's rows are stored in two halves by bit 2
   // of the row index, each in order of (row >> 3, row & 3): the eight rows a
   // lane feeds one product MFMA (r0..r0+3, r0+8..r0+11 with bit 2 = h) are then
@@ -1049,7 +1054,7 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
   const int item = xcd_item(blockIdx.x, rblocks * nsplit * ngroups);
   const int unit = item / rblocks, rb = item - unit * rblocks;
   const int split = unit / ngroups, grp = unit - split * ngroups;
-  const int nb0 = grp * NBL, nbn = min(NBL, NB - nb0);
+  const int nb0 = nb_base + grp * NBL;
   const int T = (L + kTY - 1) / kTY;
   const int t0 = split * tiles_per_split, t1 = min(T, t0 + tiles_per_split);
   const int x = (rb * WAVES + wave) * 32 + l32;
@@ -1090,7 +1095,7 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
     for (int q = 0; q < CPTT; ++q) {
       const int chunk = min(tid + q * NT, CHT - 1);
       const int cl = chunk / CCH, j = chunk % CCH;
-      const int c = min(32 * nb0 + cl, KP - 1);   // a short last group repeats a column
+      const int c = min(32 * nb0 + cl, KP - 1);
       pret[q] = *reinterpret_cast<const intx4*>(
           Yt + (int64_t)c * Lp + (int64_t)tile * kTY + 8 * j);
     }
@@ -1168,16 +1173,14 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
         }
 #pragma unroll
         for (int nb = 0; nb < NBL; ++nb) {
-          if (nb < nbn) {
-            // A operand: value column 32 (nb0 + nb) + l32 at the same eight rows
-            // (r0..r0+3, r0+8..r0+11, r0 = 32 sub + 16 ks + 4 h): positions
-            // 16 sub + 8 ks .. + 7 of half h
-            const uint8_t* col = &yt[buf][(32 * nb + l32) * TS + h * kTY + sub * 32 + ks * 16];
-            const intx4 av = *reinterpret_cast<const intx4*>(col);
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&av);
-            g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, g32[nb], 0, 0, 0);
-            g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, g32[nb], 0, 0, 0);
-          }
+          // A operand: value column 32 (nb0 + nb) + l32 at the same eight rows
+          // (r0..r0+3, r0+8..r0+11, r0 = 32 sub + 16 ks + 4 h): positions
+          // 16 sub + 8 ks .. + 7 of half h
+          const uint8_t* col = &yt[buf][(32 * nb + l32) * TS + h * kTY + sub * 32 + ks * 16];
+          const intx4 av = *reinterpret_cast<const intx4*>(col);
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&av);
+          g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, g32[nb], 0, 0, 0);
+          g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, g32[nb], 0, 0, 0);
         }
       }
     }
@@ -1200,10 +1203,8 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
     double* dst = gpart + ((int64_t)split * R + x) * KP + 32 * nb0;
 #pragma unroll
     for (int nb = 0; nb < NBL; ++nb)
-      if (nb < nbn) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) dst[32 * nb + 8 * (j >> 2) + 4 * h + (j & 3)] = g64[nb][j];
-      }
+      for (int j = 0; j < 16; ++j) dst[32 * nb + 8 * (j >> 2) + 4 * h + (j & 3)] = g64[nb][j];
   }
 }
 
@@ -1235,7 +1236,7 @@ static hipError_t grad_t(const FusedPass& fp, const int* Eptr, const double* a_o
                          int64_t ld_g, hipStream_t s) {
   constexpr int kTY = ty_for(KP * 2);
   constexpr int NB = KP / 32, NBL = grad_col_blocks(KP);
-  const int ngroups = (NB + NBL - 1) / NBL;
+  constexpr int FULL = NB / NBL, REM = NB % NBL;
   const int64_t rblocks = (fp.out.rows + kGradWaves * 32 - 1) / (kGradWaves * 32);
   const int T = (int)((fp.red.rows + kTY - 1) / kTY);
   const int Lp = T * kTY;
@@ -1244,13 +1245,22 @@ static hipError_t grad_t(const FusedPass& fp, const int* Eptr, const double* a_o
                      dim3(256), 0, s, (const uint8_t*)fp.red.ops, (int)fp.red.rows, Lp, yt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_grad_pass<KP>), dim3((unsigned)(rblocks * splits * ngroups)),
+  hipLaunchKernelGGL((k_grad_pass<KP, NBL>), dim3((unsigned)(rblocks * splits * FULL)),
                      dim3(kGradWaves * 64),
                      0, s, (const uint8_t*)fp.out.ops, (const uint8_t*)fp.red.ops,
                      (const uint16_t*)yt, Lp, fp.w_red, Eptr, fp.shift, (int)fp.out.rows,
-                     (int)fp.red.rows, tps, splits, ngroups, gpart);
+                     (int)fp.red.rows, tps, splits, FULL, 0, gpart);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if constexpr (REM > 0) {
+    hipLaunchKernelGGL((k_grad_pass<KP, REM>), dim3((unsigned)(rblocks * splits)),
+                       dim3(kGradWaves * 64),
+                       0, s, (const uint8_t*)fp.out.ops, (const uint8_t*)fp.red.ops,
+                       (const uint16_t*)yt, Lp, fp.w_red, Eptr, fp.shift, (int)fp.out.rows,
+                       (int)fp.red.rows, tps, splits, 1, FULL * NBL, gpart);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const int64_t n = fp.out.rows * width;
   hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, gpart,
                      splits, (int)fp.out.rows, (int)fp.kpad, width, Eptr, fp.shift, a_out,
