@@ -235,11 +235,12 @@ hipError_t launch_topk(const FusedPass& fp, const double* a_out, int k, int spli
                        hipStream_t s);
 // Welfare gradient of the output side, G = mu Y (N x width FP64, width = 2d):
 // BF16 operands only. Scratch: splits x rows x kpad doubles (gpart) and
-// gradient_scratch_bytes(kpad, reduced rows) bytes (yt, the column-major copy
-// of the reduced side); *Eptr is the largest binary exponent of fp.w_red.
+// gradient_scratch_bytes(kpad, reduced rows) bytes (img, the reduced side's
+// stage image: per stage, its packed rows and value columns as LDS holds
+// them, 16-byte aligned); *Eptr is the largest binary exponent of fp.w_red.
 size_t gradient_scratch_bytes(int kpad, int64_t L);
 hipError_t launch_gradient(const FusedPass& fp, const int* Eptr, const double* a_out,
-                           double inv_p, int splits, double* gpart, uint16_t* yt, int width,
+                           double inv_p, int splits, double* gpart, uint8_t* img, int width,
                            double* g, int64_t ld_g, hipStream_t s);
 hipError_t launch_stable_factors(const void* A, const void* B, ipfp_dtype dt,
                                  const float* in_scale, int64_t ld,

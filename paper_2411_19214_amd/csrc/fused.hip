@@ -962,26 +962,58 @@ hipError_t launch_topk(const FusedPass& fp, const double* a_out, int k, int spli
 // is the reduction pass followed by a second product on the matrix cores
 // (flash-attention-forward shape): the 32 x 32 tile of P, split into BF16
 // high and low parts (about 16 significant bits together), times the value
-// tile. The product needs the value rows column-contiguous, so the packed
-// reduced side is first transposed once into a column-major copy (zero past
-// the last row); each stage then copies a block of it into LDS, every column
-// split into two halves by bit 2 of the row index (padded by 16 bytes against
-// bank conflicts), so that a lane reads its eight K values as one 16-byte
-// load. The product's K order is a permutation of the
-// 32 reduced rows of a subtile that lets every lane feed its own P values as
-// the B operand. A workgroup (4 waves, one per SIMD: the FP64 sums take the
-// registers of a second) covers 128 output rows and up to four 32-column
-// blocks of G; wider rows take two column groups, each recomputing T. FP32
-// accumulators are folded into FP64 registers every IPFP_GRAD_FOLD stages; one FP64
-// partial per (split, row, column) results.
+// tile. The product needs the value rows column-contiguous and the T product
+// the packed rows; both are laid out once per call in a stage image: for
+// every stage of kTY reduced rows, the exact bytes its LDS buffers hold, pads
+// included (packed rows of LS bytes; then, per column, the stage's values in
+// two halves by bit 2 of the row index, each in order of (row >> 3, row & 3),
+// and a 16-byte pad against bank conflicts). A stage is then filled by plain
+// global-to-LDS copies (no registers, no LDS store instructions), and a lane
+// reads the eight K values of one product MFMA as one 16-byte load. The
+// product's K order is a permutation of the 32 reduced rows of a subtile that
+// lets every lane feed its own P values as the B operand. A workgroup (4
+// waves, one per SIMD: the FP64 sums take the registers of a second) covers
+// 128 output rows and up to four 32-column blocks of G; wider rows take a
+// second column group, recomputing T. FP32 accumulators are folded into FP64
+// registers every IPFP_GRAD_FOLD stages; one FP64 partial per (split, row,
+// column) results.
 
-// Column-major copy of the packed reduced side: Yt[c][y] = Yr[y][c] for
-// y < L, 0 for L <= y < Lp. Grid (Lp / 64, KP / 32), 256 threads.
+template <int KP>
+struct GradImage {
+  static constexpr int RB = KP * 2;               // bytes per packed row
+  static constexpr int kTY = ty_for(RB);          // reduced rows per stage
+  static constexpr int LS = RB + 16;              // packed row stride
+  static constexpr int TS = kTY * 2 + 16;         // bytes per column per stage
+  static constexpr int64_t YS = (int64_t)kTY * LS;      // packed rows of a stage
+  static constexpr int64_t SS = YS + (int64_t)KP * TS;  // bytes per stage
+};
+
+// Packed rows of the stage image: stage y / kTY, row y % kTY, LS bytes (the
+// row of Yr, the last row repeated past the end, then a zero pad). One thread
+// per 16-byte chunk, n = T kTY LS / 16 threads.
 template <int KP>
 __global__ void __launch_bounds__(256)
-    k_transpose_packed(const uint8_t* __restrict__ Yr, int L, int Lp,
-                       uint16_t* __restrict__ Yt) {
-  constexpr int RB = KP * 2;
+    k_grad_image_rows(const uint8_t* __restrict__ Yr, int L, int64_t n,
+                      uint8_t* __restrict__ img) {
+  typedef GradImage<KP> G;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int y = (int)(i / (G::LS / 16)), cb = (int)(i % (G::LS / 16));
+  const int tile = y / G::kTY, r = y % G::kTY;
+  intx4 v = intx4{0, 0, 0, 0};
+  if (cb < G::RB / 16)
+    v = *reinterpret_cast<const intx4*>(Yr + (int64_t)min(y, L - 1) * G::RB + cb * 16);
+  *reinterpret_cast<intx4*>(img + tile * G::SS + (int64_t)r * G::LS + cb * 16) = v;
+}
+
+// Value columns of the stage image: element e of half h of column c holds
+// Yr[stage row 8 (e / 4) + 4 h + e % 4][c] (0 past the last row). Grid
+// (Lp / 64, KP / 32), 256 threads: a block transposes 64 rows x 32 columns
+// through LDS, then each thread writes 8 values (16 bytes) of one column half.
+template <int KP>
+__global__ void __launch_bounds__(256)
+    k_grad_image_cols(const uint8_t* __restrict__ Yr, int L, uint8_t* __restrict__ img) {
+  typedef GradImage<KP> G;
   __shared__ __attribute__((aligned(16))) uint16_t tile[32][72];   // [column][row]
   const int t = threadIdx.x;
   const int y0 = blockIdx.x * 64, c0 = blockIdx.y * 32;
@@ -989,17 +1021,28 @@ __global__ void __launch_bounds__(256)
     const int r = t >> 2, j = t & 3;          // 64 rows x 4 chunks of 8 columns
     const int y = y0 + r;
     intx4 v = intx4{0, 0, 0, 0};
-    if (y < L) v = *reinterpret_cast<const intx4*>(Yr + (int64_t)y * RB + (c0 + 8 * j) * 2);
+    if (y < L) v = *reinterpret_cast<const intx4*>(Yr + (int64_t)y * G::RB + (c0 + 8 * j) * 2);
 #pragma unroll
     for (int i = 0; i < 8; ++i)
       tile[8 * j + i][r] = (uint16_t)((uint32_t)v[i >> 1] >> (16 * (i & 1)));
   }
   __syncthreads();
-  {
-    const int c = t >> 3, q = t & 7;          // 32 columns x 8 chunks of 8 rows
-    *reinterpret_cast<intx4*>(Yt + (int64_t)(c0 + c) * Lp + y0 + 8 * q) =
-        *reinterpret_cast<const intx4*>(&tile[c][8 * q]);
+  const int c = t >> 3, h = (t >> 2) & 1, k = t & 3;
+  const int stage = y0 / G::kTY, lr0 = y0 % G::kTY;   // lr0 is 0 or 64
+  const int e0 = lr0 / 2 + 8 * k;
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 8; i += 2) {
+    const int ea = e0 + i, eb = ea + 1;
+    const int ra = 8 * (ea >> 2) + 4 * h + (ea & 3) - lr0;
+    const int rb = 8 * (eb >> 2) + 4 * h + (eb & 3) - lr0;
+    w[i / 2] = (uint32_t)tile[c][ra] | ((uint32_t)tile[c][rb] << 16);
   }
+  uint8_t* col = img + stage * G::SS + G::YS + (int64_t)(c0 + c) * G::TS;
+  *reinterpret_cast<intx4*>(col + h * G::kTY + e0 * 2) =
+      intx4{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+  if (lr0 == 0 && h == 0 && k == 0)
+    *reinterpret_cast<intx4*>(col + 2 * G::kTY) = intx4{0, 0, 0, 0};
 }
 
 // Stages of FP32 product accumulation between folds into the FP64 sums: each
@@ -1014,6 +1057,27 @@ __global__ void __launch_bounds__(256)
 constexpr int grad_col_blocks(int kp) { return kp / 32 < 4 ? kp / 32 : 4; }
 constexpr int kGradWaves = 4;
 
+// Copies `bytes` (a multiple of 16) from global memory to LDS, the waves of
+// the workgroup taking 1 KiB (64 lanes x 16 bytes) each in turn: lane l of a
+// copy writes 16 bytes at the copy's LDS base + 16 l.
+template <int WAVES, int BYTES>
+__device__ __forceinline__ void stage_copy(const uint8_t* src, uint8_t* dst, int wave, int lane) {
+  static_assert(BYTES % 16 == 0, "whole 16-byte chunks");
+  constexpr int kCopies = (BYTES + 1023) / 1024;
+#pragma unroll
+  for (int i = 0; i < (kCopies + WAVES - 1) / WAVES; ++i) {
+    const int c = wave + i * WAVES;
+    if (c * 1024 + lane * 16 < BYTES)
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(src + c * 1024 + lane * 16),
+          (__attribute__((address_space(3))) void*)(dst + c * 1024), 16, 0, 0);
+  }
+}
+
+// Waits until this wave's global-to-LDS copies (and every other vector memory
+// load) have landed: vmcnt(0), expcnt and lgkmcnt left at their maxima.
+__device__ __forceinline__ void wait_vector_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // NBL 32-column blocks per workgroup, a compile-time count: the product loop
 // then has no branches, and its LDS reads and MFMAs schedule as one block.
 // Groups g = 0 .. ngroups-1 cover column blocks nb_base + NBL g onwards; a
@@ -1021,29 +1085,23 @@ constexpr int kGradWaves = 4;
 // for its last, narrower group.
 template <int KP, int NBL>
 __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-    k_grad_pass(const uint8_t* __restrict__ Xo, const uint8_t* __restrict__ Yr,
-                const uint16_t* __restrict__ Yt, int Lp, const double* __restrict__ wred,
-                const int* __restrict__ Eptr, const float* __restrict__ shift, int R, int L,
-                int tiles_per_split, int nsplit, int ngroups, int nb_base,
-                double* __restrict__ gpart) {
+    k_grad_pass(const uint8_t* __restrict__ Xo, const uint8_t* __restrict__ img,
+                const double* __restrict__ wred, const int* __restrict__ Eptr,
+                const float* __restrict__ shift, int R, int L, int tiles_per_split, int nsplit,
+                int ngroups, int nb_base, double* __restrict__ gpart) {
   constexpr int WAVES = kGradWaves;
   typedef PassCore<KP, 1, WAVES, kBF16> C;
+  typedef GradImage<KP> G;
   typedef typename C::Frag Frag;
   typedef Op<kBF16> O;
-  constexpr int RB = C::RB, kTY = C::kTY, NS = C::NS, LS = C::LS, NT = C::NT;
-  constexpr int CH = C::CH, CPT = C::CPT, SUB = C::SUB;
+  constexpr int RB = C::RB, kTY = C::kTY, NS = C::NS, LS = C::LS, SUB = C::SUB;
+  static_assert(LS == G::LS && kTY == G::kTY, "stage image layout");
   static_assert(NBL >= 1 && NBL <= 4 && NBL <= KP / 32, "column blocks per workgroup");
-  // bytes per staged column. A column's rows are stored in two halves by bit 2
-  // of the row index, each in order of (row >> 3, row & 3): the eight rows a
-  // lane feeds one product MFMA (r0..r0+3, r0+8..r0+11 with bit 2 = h) are then
-  // 16 consecutive bytes, read with one ds_read_b128, and a 16-byte pad keeps
-  // the 16 lanes of a read phase on distinct banks
-  constexpr int TS = kTY * 2 + 16;
-  constexpr int CCH = kTY * 2 / 16;         // 16-byte chunks per staged column
-  constexpr int CHT = NBL * 32 * CCH;
-  constexpr int CPTT = (CHT + NT - 1) / NT;
-  __shared__ __attribute__((aligned(16))) uint8_t ys[2][kTY * LS];
-  __shared__ __attribute__((aligned(16))) uint8_t yt[2][NBL * 32 * TS];
+  constexpr int TS = G::TS;
+  constexpr int YS = (int)G::YS;            // bytes of packed rows per stage
+  constexpr int YT = NBL * 32 * TS;         // bytes of this group's columns per stage
+  __shared__ __attribute__((aligned(16))) uint8_t ys[2][YS];
+  __shared__ __attribute__((aligned(16))) uint8_t yt[2][YT];
   __shared__ __attribute__((aligned(16))) float ws[2][kTY];
 
   int E = *Eptr;
@@ -1081,65 +1139,43 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
       g64[nb][j] = 0.0;
     }
 
-  intx4 pre[CPT], pret[CPTT];
+  // a stage's packed rows and this group's value columns, straight from the
+  // image into LDS buffer b; every thread loads the weight of row tid % kTY
+  // (duplicates store identical values)
   float pw = 0.f;
-  auto gload = [&](int tile) {
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int chunk = min(tid + q * NT, CH - 1);
-      const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
-      const uint32_t y = (uint32_t)min(tile * kTY + r, L - 1);
-      pre[q] = *reinterpret_cast<const intx4*>(Yr + cb * 16 + (uint64_t)y * RB);
-    }
-#pragma unroll
-    for (int q = 0; q < CPTT; ++q) {
-      const int chunk = min(tid + q * NT, CHT - 1);
-      const int cl = chunk / CCH, j = chunk % CCH;
-      const int c = min(32 * nb0 + cl, KP - 1);
-      pret[q] = *reinterpret_cast<const intx4*>(
-          Yt + (int64_t)c * Lp + (int64_t)tile * kTY + 8 * j);
-    }
+  auto stage_in = [&](int tile, int b) {
+    const uint8_t* src = img + (int64_t)tile * G::SS;
+    stage_copy<WAVES, YS>(src, ys[b], wave, lane);
+    stage_copy<WAVES, YT>(src + G::YS + (int64_t)32 * nb0 * TS, yt[b], wave, lane);
     const int y = tile * kTY + (tid % kTY);
     pw = y < L ? (float)ldexp(wred[min(y, L - 1)], -E) : 0.f;
   };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int chunk = min(tid + q * NT, CH - 1);
-      const int r = chunk / (RB / 16), cb = chunk % (RB / 16);
-      *reinterpret_cast<intx4*>(&ys[buf][r * LS + cb * 16]) = pre[q];
-    }
-#pragma unroll
-    for (int q = 0; q < CPTT; ++q) {
-      const int chunk = min(tid + q * NT, CHT - 1);
-      const int cl = chunk / CCH, j = chunk % CCH;
-      // rows 8j..8j+3 to the first half, 8j+4..8j+7 to the second
-      uint8_t* d = &yt[buf][cl * TS + 8 * j];
-      *reinterpret_cast<int2*>(d) = int2{pret[q][0], pret[q][1]};
-      *reinterpret_cast<int2*>(d + kTY) = int2{pret[q][2], pret[q][3]};
-    }
-    ws[buf][tid % kTY] = pw;
-  };
 
   if (t0 < t1) {
-    gload(t0);
-    lstore(0);
+    stage_in(t0, 0);
+    ws[0][tid % kTY] = pw;
   }
+  wait_vector_loads();
   __syncthreads();
-  // one subtile's T + h (an MFMA chain over the packed row)
+  // one subtile's T + h (an MFMA chain over the packed row; the first MFMA
+  // adds the loop-invariant block of h)
+  floatx16 shv;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) shv[j] = hv;
   auto tsub = [&](int buf, int sub) {
     const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
-    floatx16 acc;
+    floatx16 acc = mfma_step<kBF16>(lds_frag<kBF16>(arow, 0), bfrag[0], shv, 127, 127);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = hv;
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
+    for (int s = 1; s < NS; ++s)
       acc = mfma_step<kBF16>(lds_frag<kBF16>(arow, s), bfrag[s], acc, 127, 127);
     return acc;
   };
   for (int tile = t0; tile < t1; ++tile) {
     const int buf = (tile - t0) & 1;
-    gload(min(tile + 1, t1 - 1));
+    // the other buffer was last read before the barrier that ended the
+    // previous stage: the next stage's copies go out before this stage's work
+    const bool more = tile + 1 < t1;
+    if (more) stage_in(tile + 1, buf ^ 1);
     // the next subtile's T chain is issued ahead of this subtile's exp2 and
     // products, which do not depend on it
     floatx16 nxt = tsub(buf, 0);
@@ -1196,7 +1232,8 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
           g32[nb][j] = 0.f;
         }
     }
-    lstore(buf ^ 1);
+    if (more) ws[buf ^ 1][tid % kTY] = pw;
+    wait_vector_loads();
     __syncthreads();
   }
   if (ok) {
@@ -1226,38 +1263,43 @@ __global__ void __launch_bounds__(256)
 
 template <int KP>
 static size_t grad_t_scratch(int64_t L) {
-  constexpr int kTY = ty_for(KP * 2);
-  return (size_t)KP * (size_t)((L + kTY - 1) / kTY * kTY) * sizeof(uint16_t);
+  typedef GradImage<KP> G;
+  return (size_t)((L + G::kTY - 1) / G::kTY) * (size_t)G::SS;
 }
 
 template <int KP>
 static hipError_t grad_t(const FusedPass& fp, const int* Eptr, const double* a_out, double inv_p,
-                         int splits, double* gpart, uint16_t* yt, int width, double* g,
+                         int splits, double* gpart, uint8_t* img, int width, double* g,
                          int64_t ld_g, hipStream_t s) {
-  constexpr int kTY = ty_for(KP * 2);
+  typedef GradImage<KP> G;
+  constexpr int kTY = G::kTY;
   constexpr int NB = KP / 32, NBL = grad_col_blocks(KP);
   constexpr int FULL = NB / NBL, REM = NB % NBL;
   const int64_t rblocks = (fp.out.rows + kGradWaves * 32 - 1) / (kGradWaves * 32);
-  const int T = (int)((fp.red.rows + kTY - 1) / kTY);
+  const int L = (int)fp.red.rows;
+  const int T = (L + kTY - 1) / kTY;
   const int Lp = T * kTY;
   const int tps = (T + splits - 1) / splits;
-  hipLaunchKernelGGL((k_transpose_packed<KP>), dim3((unsigned)(Lp / 64), (unsigned)(KP / 32)),
-                     dim3(256), 0, s, (const uint8_t*)fp.red.ops, (int)fp.red.rows, Lp, yt);
+  const int64_t nrow = (int64_t)Lp * (G::LS / 16);
+  hipLaunchKernelGGL((k_grad_image_rows<KP>), dim3((unsigned)((nrow + 255) / 256)), dim3(256), 0,
+                     s, (const uint8_t*)fp.red.ops, L, nrow, img);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_grad_image_cols<KP>), dim3((unsigned)(Lp / 64), (unsigned)(KP / 32)),
+                     dim3(256), 0, s, (const uint8_t*)fp.red.ops, L, img);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_grad_pass<KP, NBL>), dim3((unsigned)(rblocks * splits * FULL)),
-                     dim3(kGradWaves * 64),
-                     0, s, (const uint8_t*)fp.out.ops, (const uint8_t*)fp.red.ops,
-                     (const uint16_t*)yt, Lp, fp.w_red, Eptr, fp.shift, (int)fp.out.rows,
-                     (int)fp.red.rows, tps, splits, FULL, 0, gpart);
+                     dim3(kGradWaves * 64), 0, s, (const uint8_t*)fp.out.ops,
+                     (const uint8_t*)img, fp.w_red, Eptr, fp.shift, (int)fp.out.rows, L, tps,
+                     splits, FULL, 0, gpart);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if constexpr (REM > 0) {
     hipLaunchKernelGGL((k_grad_pass<KP, REM>), dim3((unsigned)(rblocks * splits)),
-                       dim3(kGradWaves * 64),
-                       0, s, (const uint8_t*)fp.out.ops, (const uint8_t*)fp.red.ops,
-                       (const uint16_t*)yt, Lp, fp.w_red, Eptr, fp.shift, (int)fp.out.rows,
-                       (int)fp.red.rows, tps, splits, 1, FULL * NBL, gpart);
+                       dim3(kGradWaves * 64), 0, s, (const uint8_t*)fp.out.ops,
+                       (const uint8_t*)img, fp.w_red, Eptr, fp.shift, (int)fp.out.rows, L, tps,
+                       splits, 1, FULL * NBL, gpart);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1281,12 +1323,12 @@ size_t gradient_scratch_bytes(int kpad, int64_t L) {
 }
 
 hipError_t launch_gradient(const FusedPass& fp, const int* Eptr, const double* a_out,
-                           double inv_p, int splits, double* gpart, uint16_t* yt, int width,
+                           double inv_p, int splits, double* gpart, uint8_t* img, int width,
                            double* g, int64_t ld_g, hipStream_t s) {
   if (fp.compute != IPFP_BF16) return hipErrorInvalidValue;
   switch (fp.kpad) {
 #define IPFP_GRAD_CASE(K) \
-    case K: return grad_t<K>(fp, Eptr, a_out, inv_p, splits, gpart, yt, width, g, ld_g, s);
+    case K: return grad_t<K>(fp, Eptr, a_out, inv_p, splits, gpart, img, width, g, ld_g, s);
     IPFP_GRAD_KPADS(IPFP_GRAD_CASE)
 #undef IPFP_GRAD_CASE
     default: return hipErrorInvalidValue;

@@ -880,8 +880,8 @@ int ipfp_market_gradient(ipfp_handle* h, int side, double* g_out, int64_t ld_g,
   while (splits > 1 && (size_t)splits * R * h->kpad * sizeof(double) > ((size_t)2 << 30))
     splits /= 2;
   const size_t part = (size_t)splits * R * h->kpad * sizeof(double);
-  const size_t ytb = gradient_scratch_bytes((int)h->kpad, L);
-  const size_t bytes = align_up(sizeof(Ctl), 256) + align_up(part, 256) + ytb;
+  const size_t imgb = gradient_scratch_bytes((int)h->kpad, L);
+  const size_t bytes = align_up(sizeof(Ctl), 256) + align_up(part, 256) + imgb;
   rc = ctx_reserve(h->ctx, bytes);
   if (rc != IPFP_OK) return rc;
   char* mem = nullptr;
@@ -891,11 +891,11 @@ int ipfp_market_gradient(ipfp_handle* h, int side, double* g_out, int64_t ld_g,
   }
   Ctl* sc = (Ctl*)mem;
   double* gpart = (double*)(mem + align_up(sizeof(Ctl), 256));
-  uint16_t* yt = (uint16_t*)(mem + align_up(sizeof(Ctl), 256) + align_up(part, 256));
+  uint8_t* img = (uint8_t*)(mem + align_up(sizeof(Ctl), 256) + align_up(part, 256));
   const double inv_p = 1.0 / (double)fused_prescale(h->mk.sigma);
   rc = IPFP_OK;
   if (launch_init_exp(fp.w_red, L, sc, 0, s) != hipSuccess ||
-      launch_gradient(fp, &sc->wexp[0], a_out, inv_p, splits, gpart, yt, width, g_out, ld_g,
+      launch_gradient(fp, &sc->wexp[0], a_out, inv_p, splits, gpart, img, width, g_out, ld_g,
                       s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     rc = IPFP_EHIP;

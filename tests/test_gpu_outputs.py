@@ -158,9 +158,10 @@ def test_topk_full_width_sampled(torch, lib):
 def test_gradient_matches_oracle(torch, lib, N, M, d):
     """G = mu [V|P] and mu^T [U|Q] (envelope theorem) against the oracle on
     the same packed operands. Bound per component, from the arithmetic: P in
-    two BF16 parts (relative 2^-18), FP32 products accumulated over one stage
-    of at most 128 rows (128 x 2^-24) and folded into FP64, so
-    |G - G_ref| <= 2e-5 sum_y mu_xy |Y_y|."""
+    two BF16 parts (relative 2^-18); each FP32 accumulator takes 16 MFMA
+    additions per 128-row stage and is folded into FP64 every 4 stages
+    (64 x 2^-24), so |G - G_ref| <= 2e-5 sum_y mu_xy |Y_y| with room to spare.
+    d = 100 (2d = 200) takes the narrower second column group."""
     banner(f"gradient {N}x{M} d={d}")
     mk = workloads.factor_market(N, M, d, 1.0 / d, 0.7, "uint1-5", seed=N * 7 + M + d,
                                  name="grad")
