@@ -24,6 +24,12 @@
  * current (a, b) is recorded (eq. 5's row equation; its column equation holds
  * to rounding right after each v update). The solve stops when r < tol and
  * returns that sweep's (a, b); tol = 0 runs exactly max_sweeps sweeps.
+ * r is measured on the kernel the path computes: on the FUSED path that is
+ * 2^T of the rounded operands, summed from hardware exp2 values and FP32
+ * partial sums of 16 terms, so r settles at a floor of a few 1e-7 (the FP64
+ * oracle on the same operands agrees to 3e-7): a tol below that floor
+ * returns IPFP_NOT_CONVERGED after max_sweeps. The distance to the exact
+ * surplus (ipfp_margin_residuals) is set by the operand rounding instead.
  *
  * Conventions for every entry point:
  *  - Return value: IPFP_OK (0), a positive status (results valid), or a
