@@ -324,9 +324,11 @@ int ipfp_market_topk(ipfp_handle *h, int side, int32_t k, int32_t *idx_out,
  * mu = 2^T a b with T from the packed rows, and the packed rows divided by
  * their prescale as the factor values (the factors as the matrix cores see
  * them). g_out: rows x 2d FP64 device, row stride ld_g >= 2d. Scratch of
- * splits x rows x kpad doubles plus a column-major copy of the other side's
- * packed rows (kpad x its row count, rounded up to the stage height, 2 bytes
- * each) is allocated for the call and charged to the context budget.
+ * splits x rows x kpad doubles plus a stage image of the other side's packed
+ * rows (its rows and its value columns laid out per stage as the kernel's
+ * LDS holds them: (2 kpad + 16) + kpad (2 s + 16) / s bytes per row for
+ * stage height s, 544 at kpad 128; its row count rounded up to the stage
+ * height) is allocated for the call and charged to the context budget.
  * IPFP_EINVAL for the plain path or FP8 operands. */
 int ipfp_market_gradient(ipfp_handle *h, int side, double *g_out, int64_t ld_g,
                          void *stream);

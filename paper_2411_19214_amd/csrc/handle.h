@@ -66,7 +66,7 @@ struct ipfp_handle {
   bool arena = false;            // `mem` belongs to a serving arena, not this handle
   ipfp::Ctl* ctl = nullptr;
   double* hist = nullptr;
-  double* res_block = nullptr;   // row residual maxima (combine + fixup slots)
+  double* res_block = nullptr;   // row residual maxima, one per row-combine workgroup
   double* res_dummy = nullptr;   // column side writes its (unused) maxima here
   double* u2 = nullptr;          // 2 x N double buffer
   double* v = nullptr;           // M
