@@ -154,14 +154,18 @@ def test_topk_full_width_sampled(torch, lib):
 
 
 @pytest.mark.parametrize("N,M,d", [(1000, 700, 32), (333, 2050, 64), (257, 20000, 32),
-                                   (130, 90, 50), (64, 70, 100), (100, 41, 128)])
+                                   (130, 90, 50), (64, 70, 100), (100, 41, 128),
+                                   (300, 500, 16), (200, 333, 48), (150, 260, 80),
+                                   (170, 129, 96)])
 def test_gradient_matches_oracle(torch, lib, N, M, d):
     """G = mu [V|P] and mu^T [U|Q] (envelope theorem) against the oracle on
     the same packed operands. Bound per component, from the arithmetic: P in
     two BF16 parts (relative 2^-18); each FP32 accumulator takes 16 MFMA
     additions per 128-row stage and is folded into FP64 every 4 stages
     (64 x 2^-24), so |G - G_ref| <= 2e-5 sum_y mu_xy |Y_y| with room to spare.
-    d = 100 (2d = 200) takes the narrower second column group."""
+    The widths cover every column-group layout: 2d = 32, 64, 96 (one group of
+    1-3 blocks), 128 and 256 (full groups of 4), and 160, 200, 192 (a full
+    group and a narrower second one of 1, 3 and 2 blocks)."""
     banner(f"gradient {N}x{M} d={d}")
     mk = workloads.factor_market(N, M, d, 1.0 / d, 0.7, "uint1-5", seed=N * 7 + M + d,
                                  name="grad")
