@@ -445,10 +445,12 @@ def run_tune_serving(torch, L, count=128, repeats=3):
 
 def run_probes(torch, L):
     """The roofline probes (ipfp_probe): exp2 results/s, dense MFMA flop/s of
-    the BF16, FP8 and FP32 instructions the fused passes use, and the
-    streaming HBM read rate."""
+    the BF16, FP8 and FP32 instructions the fused passes use, the streaming
+    HBM read rate, and the matrix stream at the passes' occupancy bare and
+    with their exp2/FMA epilogue beside it."""
     out = {}
-    for kind in ("exp2", "mfma_bf16", "mfma_fp8", "mfma_f32", "hbm_read"):
+    for kind in ("exp2", "mfma_bf16", "mfma_fp8", "mfma_f32", "hbm_read", "mfma_bf16_2w",
+                 "mfma_bf16_epi", "mfma_fp8_epi"):
         L.probe(kind)
         rate, ms = L.probe(kind)
         out[kind] = {"rate": rate, "ms": ms,

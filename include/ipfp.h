@@ -365,13 +365,22 @@ int ipfp_pack_side(ipfp_ctx *ctx, int64_t rows, int64_t d, ipfp_dtype in_dtype,
  *         lane-contiguous as in the plain path, four in flight per thread) of
  *         a `work`-byte buffer (a multiple of 32 MiB, allocated for the call
  *         and charged to the context budget).
+ *   MFMA_BF16_2W / MFMA_BF16_EPI / MFMA_FP8_EPI: the matrix stream at the
+ *         fused passes' occupancy (two waves per SIMD, two independent
+ *         accumulators per wave), bare or with the sum pass's epilogue beside
+ *         it: after each MFMA, 2 exp2 and 2 FMAs (BF16, the ratio at
+ *         2d = 128) or 8 exp2 and 8 FMAs (FP8 at 2d = 128), on independent
+ *         registers; MFMA flops per second, `work` = rounds of two MFMAs.
  * *rate_out receives the rate, *ms_out (may be NULL) the timed launch. */
 enum {
   IPFP_PROBE_EXP2 = 0,
   IPFP_PROBE_MFMA_BF16 = 1,
   IPFP_PROBE_MFMA_FP8 = 2,
   IPFP_PROBE_MFMA_F32 = 3,
-  IPFP_PROBE_HBM_READ = 4
+  IPFP_PROBE_HBM_READ = 4,
+  IPFP_PROBE_MFMA_BF16_2W = 5,
+  IPFP_PROBE_MFMA_BF16_EPI = 6,
+  IPFP_PROBE_MFMA_FP8_EPI = 7
 };
 int ipfp_probe(ipfp_ctx *ctx, int kind, int64_t work, double *rate_out, double *ms_out,
                void *stream);

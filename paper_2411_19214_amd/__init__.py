@@ -468,12 +468,18 @@ def footprint(N, M, d, path="fused", compute=None, splits=0, tile_rows=0) -> int
 
 _PROBES = {"exp2": (_lib.PROBE_EXP2, 200000), "mfma_bf16": (_lib.PROBE_MFMA_BF16, 40000),
            "mfma_fp8": (_lib.PROBE_MFMA_FP8, 20000), "mfma_f32": (_lib.PROBE_MFMA_F32, 10000),
-           "hbm_read": (_lib.PROBE_HBM_READ, 16 << 30)}
+           "hbm_read": (_lib.PROBE_HBM_READ, 16 << 30),
+           "mfma_bf16_2w": (_lib.PROBE_MFMA_BF16_2W, 1500000),
+           "mfma_bf16_epi": (_lib.PROBE_MFMA_BF16_EPI, 1000000),
+           "mfma_fp8_epi": (_lib.PROBE_MFMA_FP8_EPI, 500000)}
 
 
 def probe(kind: str, work: int = 0, stream=None, ctx=None):
     """A roofline probe (``ipfp_probe``): (rate, ms). kind: "exp2" (results/s),
-    "mfma_bf16" / "mfma_fp8" / "mfma_f32" (flop/s), "hbm_read" (bytes/s)."""
+    "mfma_bf16" / "mfma_fp8" / "mfma_f32" (flop/s), "hbm_read" (bytes/s), and
+    the matrix stream at the passes' occupancy, bare ("mfma_bf16_2w") or with
+    the sum pass's exp2/FMA epilogue beside it ("mfma_bf16_epi",
+    "mfma_fp8_epi"), in MFMA flop/s."""
     code, default = _PROBES[kind]
     rate, ms = ctypes.c_double(), ctypes.c_double()
     ctx = ctx or Context.default(0)

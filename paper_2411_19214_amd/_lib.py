@@ -165,6 +165,7 @@ SIGNATURES = {
 }
 
 PROBE_EXP2, PROBE_MFMA_BF16, PROBE_MFMA_FP8, PROBE_MFMA_F32, PROBE_HBM_READ = 0, 1, 2, 3, 4
+PROBE_MFMA_BF16_2W, PROBE_MFMA_BF16_EPI, PROBE_MFMA_FP8_EPI = 5, 6, 7
 
 _LIB = None
 

@@ -106,6 +106,77 @@ __global__ void __launch_bounds__(kProbeThreads) k_probe_mfma(int iters, float* 
   out[(int64_t)blockIdx.x * kProbeThreads + threadIdx.x] = s;
 }
 
+// The matrix stream beside the fused passes' epilogue, at the passes'
+// occupancy: 4-wave workgroups holding 64 KiB of LDS each, so two share a
+// compute unit (two waves per SIMD), 2 workgroups per compute unit in all.
+// Per round each wave issues two MFMAs on independent accumulators (the
+// passes' paired chains), each followed by NE exp2 and NE FMAs on 16
+// independent chains (x = 2^-x stays in [0.5, 1]); scheduling groups keep
+// that order. NE = 0 is the bare matrix stream at this occupancy. The rate is
+// the MFMA flops per second.
+constexpr int kMixLds = 64 * 1024;
+constexpr int kMixBlocks = 256 * 2;
+
+template <int KIND, int NE>
+__global__ void __launch_bounds__(kProbeThreads) k_probe_mix(int iters, float* out) {
+  extern __shared__ float mix_lds[];
+  floatx16 c[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c[j][r] = 0.f;
+  const uint32_t seed = blockIdx.x * kProbeThreads + threadIdx.x;
+  float x[16], sum[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    x[q] = 0.5f + 0.03f * (float)q + 0.001f * (float)(threadIdx.x & 15);
+    sum[q] = 0.f;
+  }
+  const float w = rand_val(mix32(seed));
+  bf16x8 a, b;
+  intx8 a8, b8;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    a[k] = (__bf16)rand_val(mix32(seed * 16 + k));
+    b[k] = (__bf16)rand_val(mix32(seed * 16 + 8 + k));
+    a8[k] = (int)(mix32(seed * 16 + k) & 0xF7F7F7F7u);
+    b8[k] = (int)(mix32(seed * 16 + 8 + k) & 0xF7F7F7F7u);
+  }
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if constexpr (KIND == 0)
+        c[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c[j], 0, 0, 0);
+      else
+        c[j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c[j], 0, 0, 0, 127, 0, 127);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int q = (j * NE + e) % 16;
+        x[q] = __builtin_amdgcn_exp2f(-x[q]);
+        sum[q] = fmaf(x[q], w, sum[q]);
+      }
+    }
+    if constexpr (NE > 0) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x400, NE, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, NE, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s += c[j][r];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s += sum[q];
+  if (threadIdx.x == 0) mix_lds[0] = s;   // the workgroup's LDS is held, not used
+  out[(int64_t)blockIdx.x * kProbeThreads + threadIdx.x] = s;
+}
+
 // Grid-stride streaming read of n16 16-byte chunks: each wave load covers 1 KiB
 // of consecutive bytes (the plain path's access pattern), four loads in
 // flight per thread (n16 a multiple of 4 x the grid's threads).
@@ -132,7 +203,7 @@ using namespace ipfp;
 
 extern "C" int ipfp_probe(ipfp_ctx* ctx, int kind, int64_t work, double* rate_out,
                           double* ms_out, void* stream) {
-  if (!ctx || !rate_out || kind < IPFP_PROBE_EXP2 || kind > IPFP_PROBE_HBM_READ || work < 1)
+  if (!ctx || !rate_out || kind < IPFP_PROBE_EXP2 || kind > IPFP_PROBE_MFMA_FP8_EPI || work < 1)
     return IPFP_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (hipSetDevice(ctx->device) != hipSuccess) return IPFP_EHIP;
@@ -167,6 +238,18 @@ extern "C" int ipfp_probe(ipfp_ctx* ctx, int kind, int64_t work, double* rate_ou
       case IPFP_PROBE_MFMA_F32:
         hipLaunchKernelGGL(k_probe_mfma<2>, dim3(kProbeBlocks), dim3(kProbeThreads), 0, s, iters, out);
         break;
+      case IPFP_PROBE_MFMA_BF16_2W:
+        hipLaunchKernelGGL((k_probe_mix<0, 0>), dim3(kMixBlocks), dim3(kProbeThreads), kMixLds, s,
+                           iters, out);
+        break;
+      case IPFP_PROBE_MFMA_BF16_EPI:
+        hipLaunchKernelGGL((k_probe_mix<0, 2>), dim3(kMixBlocks), dim3(kProbeThreads), kMixLds, s,
+                           iters, out);
+        break;
+      case IPFP_PROBE_MFMA_FP8_EPI:
+        hipLaunchKernelGGL((k_probe_mix<1, 8>), dim3(kMixBlocks), dim3(kProbeThreads), kMixLds, s,
+                           iters, out);
+        break;
       default:
         hipLaunchKernelGGL(k_probe_read, dim3(kProbeBlocks), dim3(kProbeThreads), 0, s, buf,
                            work / 16, out);
@@ -194,6 +277,13 @@ extern "C" int ipfp_probe(ipfp_ctx* ctx, int kind, int64_t work, double* rate_ou
     case IPFP_PROBE_MFMA_BF16: units = waves * 4.0 * iters * (2.0 * 32 * 32 * 16); break;
     case IPFP_PROBE_MFMA_FP8: units = waves * 4.0 * iters * (2.0 * 32 * 32 * 64); break;
     case IPFP_PROBE_MFMA_F32: units = waves * 4.0 * iters * (2.0 * 32 * 32 * 2); break;
+    case IPFP_PROBE_MFMA_BF16_2W:
+    case IPFP_PROBE_MFMA_BF16_EPI:
+      units = (double)kMixBlocks * (kProbeThreads / 64) * 2.0 * iters * (2.0 * 32 * 32 * 16);
+      break;
+    case IPFP_PROBE_MFMA_FP8_EPI:
+      units = (double)kMixBlocks * (kProbeThreads / 64) * 2.0 * iters * (2.0 * 32 * 32 * 64);
+      break;
     default: units = (double)work; break;
   }
   *rate_out = units / (ms * 1e-3);
