@@ -595,6 +595,17 @@ def main():
     }
     if r["outputs"] is not None:
         line["outputs"] = r["outputs"]
+    # the ceiling of the pass's own instruction mix on this device: the BF16
+    # matrix stream at the pass's occupancy with its exp2/FMA epilogue beside
+    # it (ipfp_probe, about 0.1 s per launch; outside the timed region)
+    L.probe("mfma_bf16_epi")
+    mix_rate, _ = L.probe("mfma_bf16_epi")
+    line["roofline"]["mix_ceiling"] = {
+        "probe": "mfma_bf16_epi", "achieved": mix_rate / 1e12, "unit": "TFLOP/s",
+        "frac_of_peak": mix_rate / 1e12 / PEAK_BF16_TFLOPS,
+        "pass_frac_of_ceiling": achieved_tflops / (mix_rate / 1e12)}
+    log(f"mix ceiling {mix_rate / 1e12:.0f} TFLOP/s; the pass reaches "
+        f"{achieved_tflops / (mix_rate / 1e12):.3f} of it")
     if not args.no_c2:
         log("C2: plain FP32 vs fused BF16, 500 sweeps")
         line["c2_20k"] = run_c2(torch, L)
