@@ -211,9 +211,13 @@ constexpr int pass_min_waves(int ok) { return ok == kF32 ? 1 : 2; }
 constexpr int ty_for(int row_bytes) { return row_bytes <= 256 ? IPFP_TY : IPFP_TY / 2; }
 
 // Register budget: two 32-row output tiles per wave while the operand
-// fragments of both fit in 64 VGPRs per lane (one tile for FP32).
+// fragments of both fit in 64 VGPRs per lane (one tile for FP32): BF16 rows
+// up to 2d = 128, FP8 rows up to 2d = 256. Two tiles per wave halve the LDS
+// fragment reads per MFMA; with one tile the fragment reads of a compute
+// unit's four SIMDs alone take the LDS bandwidth (MI355X: C5 FP8, kpad 256,
+// 91.7 ms per pass with one tile, 81.5 ms with two).
 constexpr int xt_for(int kp, int ok) {
-  return ok == kF32 ? 1 : ((ok == kFP8 ? kp <= 128 : (kp <= 128 && kp != 96)) ? 2 : 1);
+  return ok == kF32 ? 1 : ((ok == kFP8 ? kp <= 256 : (kp <= 128 && kp != 96)) ? 2 : 1);
 }
 
 static int op_kind(ipfp_dtype compute) {
