@@ -239,6 +239,8 @@ hipError_t launch_topk(const FusedPass& fp, const double* a_out, int k, int spli
 // stage image: per stage, its packed rows and value columns as LDS holds
 // them, 16-byte aligned); *Eptr is the largest binary exponent of fp.w_red.
 size_t gradient_scratch_bytes(int kpad, int64_t L);
+// Split count of the gradient pass (at most max_splits), from its occupancy.
+int gradient_splits(int64_t R, int64_t L, int kpad, int max_splits);
 hipError_t launch_gradient(const FusedPass& fp, const int* Eptr, const double* a_out,
                            double inv_p, int splits, double* gpart, uint8_t* img, int width,
                            double* g, int64_t ld_g, hipStream_t s);

@@ -1054,7 +1054,7 @@ __global__ void __launch_bounds__(256)
 // high and low parts), so a fold every F stages bounds its rounding at about
 // 16 F x 2^-24 of the folded terms' magnitudes.
 #ifndef IPFP_GRAD_FOLD
-#define IPFP_GRAD_FOLD 4
+#define IPFP_GRAD_FOLD 8
 #endif
 
 // 32-column blocks of G per workgroup (at most), and waves per workgroup
@@ -1315,6 +1315,63 @@ static hipError_t grad_t(const FusedPass& fp, const int* Eptr, const double* a_o
 }
 
 #define IPFP_GRAD_KPADS(X) X(32) X(64) X(96) X(128) X(160) X(192) X(224) X(256)
+
+// Workgroups of the gradient pass (its full column groups) that one compute
+// unit holds at once (HIP occupancy query; 1 when the query fails).
+template <int KP>
+static int grad_wgs_per_cu() {
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &n, reinterpret_cast<const void*>(&k_grad_pass<KP, grad_col_blocks(KP)>), kGradWaves * 64,
+      0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n > 0 ? n : 1;
+}
+
+// Split count of the gradient pass, as fused_pass_splits does for the sum
+// pass but with the gradient's own occupancy (one 140 KB workgroup per
+// compute unit at kpad 128) and at most max_splits: minimises (waves of
+// workgroups) x (stages per workgroup + 1), at least 8 stages per split, the
+// smaller count on ties. At N = M = 10^6, d = 64 three splits leave the last
+// wave of workgroups half full instead of a one-split grid's 52 %.
+int gradient_splits(int64_t R, int64_t L, int kpad, int max_splits) {
+  int per_cu = 1;
+  switch (kpad) {
+#define IPFP_GRAD_OCC(K) \
+    case K: per_cu = grad_wgs_per_cu<K>(); break;
+    IPFP_GRAD_KPADS(IPFP_GRAD_OCC)
+#undef IPFP_GRAD_OCC
+    default: break;
+  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  const int64_t slots = (int64_t)cus * per_cu;
+  const int nb = kpad / 32, nbl = grad_col_blocks(kpad);
+  const int64_t groups = nb / nbl + (nb % nbl ? 1 : 0);
+  const int64_t rblocks = (R + kGradWaves * 32 - 1) / (kGradWaves * 32);
+  const int stage = ty_for(kpad * 2);
+  const int64_t T = (L + stage - 1) / stage;
+  int best = 1;
+  int64_t best_cost = INT64_MAX;
+  for (int S = 1; S <= max_splits; ++S) {
+    if (S > 1 && T / S < 8) break;
+    const int64_t waves = (rblocks * groups * S + slots - 1) / slots;
+    const int64_t cost = waves * ((T + S - 1) / S + 1);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = S;
+    }
+  }
+  return best;
+}
 
 size_t gradient_scratch_bytes(int kpad, int64_t L) {
   switch (kpad) {

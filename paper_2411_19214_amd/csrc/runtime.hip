@@ -876,9 +876,10 @@ int ipfp_market_gradient(ipfp_handle* h, int side, double* g_out, int64_t ld_g,
   fp.red_dbuf = 0;
   const double* a_out = side == 0 ? u : h->v;
   const int64_t R = fp.out.rows, L = fp.red.rows;
-  int splits = fused_auto_splits(R, L, 128);
-  while (splits > 1 && (size_t)splits * R * h->kpad * sizeof(double) > ((size_t)2 << 30))
-    splits /= 2;
+  // FP64 partials of at most 4 GiB
+  const size_t per_split = (size_t)R * h->kpad * sizeof(double);
+  const int max_splits = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 30) / per_split));
+  const int splits = gradient_splits(R, L, (int)h->kpad, max_splits);
   const size_t part = (size_t)splits * R * h->kpad * sizeof(double);
   const size_t imgb = gradient_scratch_bytes((int)h->kpad, L);
   const size_t bytes = align_up(sizeof(Ctl), 256) + align_up(part, 256) + imgb;
