@@ -86,7 +86,8 @@ def test_fused_bf16_ragged_shapes(torch, lib, N, M, d):
     np.testing.assert_allclose(info.residuals, r.res_hist, rtol=5e-3, atol=3e-7)
 
 
-@pytest.mark.parametrize("N,M,d", [(33, 257, 32), (1000, 700, 64), (500, 300, 128)])
+@pytest.mark.parametrize("N,M,d", [(33, 257, 32), (1000, 700, 64), (500, 300, 128),
+                                   (321, 1201, 96), (777, 130, 80)])
 def test_fused_fp8_ragged_shapes(torch, lib, N, M, d):
     banner(f"fused fp8 {N}x{M} d={d}")
     mk = workloads.factor_market(N, M, d, 1.0 / d, 1.0, "uint1-5", seed=N + M + d)
