@@ -81,6 +81,28 @@ def test_mix_equals_alone_bitwise(torch, lib, compute, widths):
         assert r.t_submit <= r.t_admit <= r.t_done
 
 
+# wide FP8 rows: packed widths 192 and 256, which run two output tiles per
+# wave in the grouped pass as in the single-market one
+WIDE = [(700, 1300, 128, 1.0, 1e-6, 40, 1), (1500, 900, 96, 0.5, 1e-6, 40, 1),
+        (3100, 2900, 128, 1.0, 0.0, 9, 3), (20000, 9000, 80, 1.0, 1e-6, 30, 2)]
+
+
+def test_wide_fp8_mix_equals_alone_bitwise(torch, lib):
+    banner("serve wide fp8 mix vs alone")
+    mks = [mix_market(100 + i, *s[:4]) for i, s in enumerate(WIDE)]
+    tens = [market_tensors(torch, mk) for mk in mks]
+    with lib.Server(compute="fp8", chunk=3, lanes=2) as srv:
+        reqs = [srv.submit(*t, s[3], tol=s[4], max_sweeps=s[5], check_every=s[6])
+                for t, s in zip(tens, WIDE)]
+        for r in reqs:
+            srv.wait(r, timeout_ms=60_000)
+    for t, s, r in zip(tens, WIDE, reqs):
+        a, b, info = alone(torch, lib, t, s, "fp8")
+        assert r.status == info.status, (s, r.status, info.status)
+        assert r.info.sweeps == info.sweeps and r.info.residuals == info.residuals, s
+        assert torch.equal(r.a, a) and torch.equal(r.b, b), s
+
+
 def test_serving_tuner_choice_keeps_results(torch, lib, tmp_path):
     """The serving-width tuner runs a small mix over its candidates and caches
     a choice; a server with those widths still returns every request's
