@@ -136,6 +136,35 @@ def test_topk_lists_match_oracle(torch, lib, N, M, d, compute, k):
         check_lists(idx.cpu().numpy(), score.cpu().numpy(), ref, k)
 
 
+@pytest.mark.parametrize("compute,k,ties", [("bf16", 10, False), ("fp8", 32, False),
+                                            ("bf16", 12, True)])
+def test_topk_long_rows_match_oracle(torch, lib, compute, k, ties):
+    """256 rows over a reduced side of 70,000 rows (about 550 stages per
+    workgroup, so the lists fill early and then take rare insertions), every
+    row against the oracle as in the small cases; with `ties` the reduced
+    rows repeat 50 distinct factor rows, so exact ties sit at the k-th
+    position."""
+    import dataclasses
+    banner(f"topk 256x70000 {compute} k={k} ties={ties}")
+    N, M, d = 256, 70_000, 32
+    mk = workloads.factor_market(N, M, d, 1.0 / d, 0.5, "uint1-5", seed=7000 + k, name="seed")
+    if ties:
+        pool = np.random.default_rng(5).integers(0, 50, M)
+        mk = dataclasses.replace(mk, V=np.ascontiguousarray(mk.V[pool]),
+                                 P=np.ascontiguousarray(mk.P[pool]))
+    t = market_tensors(torch, mk)
+    with lib.Market(*t, mk.sigma, tol=1e-6, max_sweeps=60, compute=compute) as h:
+        while not h.run(20):
+            pass
+        a, b, _ = h.read()
+        idx, score = h.topk(k, 0)
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    X = quant.packed_rows(np.concatenate([mk.U, mk.Q], 1), mk.sigma, compute)
+    Y = quant.packed_rows(np.concatenate([mk.V, mk.P], 1), mk.sigma, compute)
+    logmu = np.log(2.0) * (X @ Y.T + np.log2(a)[:, None] + np.log2(b)[None, :])
+    check_lists(idx.cpu().numpy(), score.cpu().numpy(), logmu, k)
+
+
 def test_topk_full_width_sampled(torch, lib):
     """N = M = 200,000 (grid of many splits): sampled rows against the oracle."""
     banner("topk 200k sampled rows")
