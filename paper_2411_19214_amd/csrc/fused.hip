@@ -1135,13 +1135,22 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
   const float hv = ok ? shift[x] : 0.f;
   floatx16 g32[NBL];
   double g64[NBL][16];
+  {
+    // The FP32 product sums start as the result of an MFMA (of zeros), like
+    // every later value they take. Started from constant zeros, they were
+    // kept in vector registers across the stage loop and copied to and from
+    // the accumulator registers at every stage (128 moves per stage).
+    const bf16x8 z = {};
+    floatx16 c0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) c0[j] = 0.f;
+#pragma unroll
+    for (int nb = 0; nb < NBL; ++nb) g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(z, z, c0, 0, 0, 0);
+  }
 #pragma unroll
   for (int nb = 0; nb < NBL; ++nb)
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      g32[nb][j] = 0.f;
-      g64[nb][j] = 0.0;
-    }
+    for (int j = 0; j < 16; ++j) g64[nb][j] = 0.0;
 
   // a stage's packed rows and this group's value columns, straight from the
   // image into LDS buffer b; every thread loads the weight of row tid % kTY
@@ -1166,13 +1175,18 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
   floatx16 shv;
 #pragma unroll
   for (int j = 0; j < 16; ++j) shv[j] = hv;
-  auto tsub = [&](int buf, int sub) {
-    const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
-    floatx16 acc = mfma_step<kBF16>(lds_frag<kBF16>(arow, 0), bfrag[0], shv, 127, 127);
+  // TP subtiles' chains at a time, interleaved k-step by k-step (two when a
+  // stage has four or more subtiles), so consecutive MFMAs are independent
+  constexpr int TP = SUB >= 4 ? 2 : 1;
+  auto tgrp = [&](int buf, int sub, floatx16 (&out)[TP]) {
 #pragma unroll
-    for (int s = 1; s < NS; ++s)
-      acc = mfma_step<kBF16>(lds_frag<kBF16>(arow, s), bfrag[s], acc, 127, 127);
-    return acc;
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int u = 0; u < TP; ++u) {
+        const uint8_t* arow = &ys[buf][((sub + u) * 32 + l32) * LS + h * O::SB];
+        out[u] = mfma_step<kBF16>(lds_frag<kBF16>(arow, s), bfrag[s], s == 0 ? shv : out[u],
+                                  127, 127);
+      }
   };
   for (int tile = t0; tile < t1; ++tile) {
     const int buf = (tile - t0) & 1;
@@ -1180,13 +1194,18 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
     // previous stage: the next stage's copies go out before this stage's work
     const bool more = tile + 1 < t1;
     if (more) stage_in(tile + 1, buf ^ 1);
-    // the next subtile's T chain is issued ahead of this subtile's exp2 and
-    // products, which do not depend on it
-    floatx16 nxt = tsub(buf, 0);
+    // the next group's T chains are issued ahead of this group's exp2 and
+    // products, which do not depend on them
+    floatx16 nxt[TP], cur[TP];
+    tgrp(buf, 0, nxt);
 #pragma unroll
     for (int sub = 0; sub < SUB; ++sub) {
-      const floatx16 acc = nxt;
-      if (sub + 1 < SUB) nxt = tsub(buf, sub + 1);
+      if (sub % TP == 0) {
+#pragma unroll
+        for (int u = 0; u < TP; ++u) cur[u] = nxt[u];
+        if (sub + TP < SUB) tgrp(buf, sub + TP, nxt);
+      }
+      const floatx16 acc = cur[sub % TP];
       float p[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
@@ -1211,17 +1230,26 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
           bl[i] = lv[0];
           bl[i + 1] = lv[1];
         }
-#pragma unroll
-        for (int nb = 0; nb < NBL; ++nb) {
-          // A operand: value column 32 (nb0 + nb) + l32 at the same eight rows
-          // (r0..r0+3, r0+8..r0+11, r0 = 32 sub + 16 ks + 4 h): positions
-          // 16 sub + 8 ks .. + 7 of half h
+        // A operand: value column 32 (nb0 + nb) + l32 at the same eight rows
+        // (r0..r0+3, r0+8..r0+11, r0 = 32 sub + 16 ks + 4 h): positions
+        // 16 sub + 8 ks .. + 7 of half h
+        auto colfrag = [&](int nb) {
           const uint8_t* col = &yt[buf][(32 * nb + l32) * TS + h * kTY + sub * 32 + ks * 16];
           const intx4 av = *reinterpret_cast<const intx4*>(col);
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&av);
-          g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, g32[nb], 0, 0, 0);
-          g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, g32[nb], 0, 0, 0);
-        }
+          return *reinterpret_cast<const bf16x8*>(&av);
+        };
+        // all column blocks' high parts, then their low parts: consecutive
+        // MFMAs never accumulate into the same sums, and each sum still
+        // takes hi before lo, k-step 0 before 1
+        bf16x8 acol[NBL];
+#pragma unroll
+        for (int nb = 0; nb < NBL; ++nb) acol[nb] = colfrag(nb);
+#pragma unroll
+        for (int nb = 0; nb < NBL; ++nb)
+          g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(acol[nb], bh, g32[nb], 0, 0, 0);
+#pragma unroll
+        for (int nb = 0; nb < NBL; ++nb)
+          g32[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(acol[nb], bl, g32[nb], 0, 0, 0);
       }
     }
     // lane (o, h) holds columns 32 (nb0 + nb) + 8 (j / 4) + 4 h + j % 4 of row o;
