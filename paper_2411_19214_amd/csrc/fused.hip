@@ -714,8 +714,21 @@ __device__ __forceinline__ void topk_insert(float (&ts)[KT], int (&ti)[KT], floa
   }
 }
 
+// Subtiles whose score chains a top-k pass interleaves (consecutive MFMAs
+// then never wait on each other): two for BF16 rows of 2d = 96 and 128 with
+// lists of up to 16, which still fit the two waves per SIMD that one chain
+// ran at; else one. MI355X, N = M = 1e6, k = 10, one chain -> two: BF16
+// 2d = 128 332 -> 327 ms, 2d = 96 282 -> 278 ms, 2d = 64 unchanged; FP8
+// 2d = 128 and 192 3 % slower (their MFMA is half as long, and the check
+// work dominates).
+template <int KP, int OK, int KT>
+constexpr int topk_tp() {
+  return PassCore<KP, 1, 4, OK>::SUB >= 4 && OK == kBF16 && KP >= 96 && KT <= 16 ? 2 : 1;
+}
+
 template <int KP, int OK, int KT>
 __global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(topk_tp<KP, OK, KT>(), topk_tp<KP, OK, KT>() == 2 ? 2 : 8)))
     k_topk_pass(const uint8_t* __restrict__ Xo, const float* __restrict__ xscale,
                 const uint8_t* __restrict__ Yr, const float* __restrict__ yscale,
                 const double* __restrict__ wred, int R, int L, int tiles_per_split,
@@ -798,29 +811,41 @@ __global__ void __launch_bounds__(256)
     lstore(0);
   }
   __syncthreads();
-  // one subtile's T (an MFMA chain over the packed row)
-  auto tsub = [&](int buf, int sub) {
-    const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
-    const int asc = FP8 ? ysc[buf][sub * 32 + l32] : 127;
-    floatx16 acc;
+  // T of TP subtiles (MFMA chains over the packed rows), interleaved k-step
+  // by k-step so that consecutive MFMAs are independent
+  constexpr int TP = topk_tp<KP, OK, KT>();
+  auto tgrp = [&](int buf, int sub, floatx16 (&out)[TP]) {
+    int asc[TP];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int u = 0; u < TP; ++u) {
+      asc[u] = FP8 ? ysc[buf][(sub + u) * 32 + l32] : 127;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) out[u][r] = 0.f;
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      acc = mfma_step<OK>(lds_frag<OK>(arow, s), bfrag[s], acc, asc, xsc);
-    return acc;
+#pragma unroll
+      for (int u = 0; u < TP; ++u) {
+        const uint8_t* arow = &ys[buf][((sub + u) * 32 + l32) * LS + h * O::SB];
+        out[u] = mfma_step<OK>(lds_frag<OK>(arow, s), bfrag[s], out[u], asc[u], xsc);
+      }
   };
   for (int tile = t0; tile < t1; ++tile) {
     const int buf = (tile - t0) & 1;
     gload(min(tile + 1, t1 - 1));
-    // the next subtile's MFMA chain is issued before this one's scores are
+    // the next group's MFMA chains are issued before this group's scores are
     // checked, and the common case (no score above any lane's k-th best)
-    // takes a single branch per subtile, so the chain runs under the checks
-    floatx16 nxt = tsub(buf, 0);
+    // takes a single branch per subtile, so the chains run under the checks
+    floatx16 nxt[TP], cur[TP];
+    tgrp(buf, 0, nxt);
 #pragma unroll
     for (int sub = 0; sub < SUB; ++sub) {
-      const floatx16 acc = nxt;
-      if (sub + 1 < SUB) nxt = tsub(buf, sub + 1);
+      if (sub % TP == 0) {
+#pragma unroll
+        for (int u = 0; u < TP; ++u) cur[u] = nxt[u];
+        if (sub + TP < SUB) tgrp(buf, sub + TP, nxt);
+      }
+      const floatx16 acc = cur[sub % TP];
       float sc[16];
       float top = -INFINITY;
 #pragma unroll
