@@ -1248,9 +1248,11 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
   floatx16 shv;
 #pragma unroll
   for (int j = 0; j < 16; ++j) shv[j] = hv;
-  // TP subtiles' chains at a time, interleaved k-step by k-step (two when a
-  // stage has four or more subtiles), so consecutive MFMAs are independent
-  constexpr int TP = SUB >= 4 ? 2 : 1;
+  // TP subtiles' chains at a time, interleaved k-step by k-step, so that
+  // consecutive MFMAs are independent: all four of a stage when it has four
+  // (MI355X, C3: 912 ms with one chain at a time, 874 with two, 849 with
+  // four, the same sums bit for bit), else one
+  constexpr int TP = SUB >= 4 ? 4 : 1;
   auto tgrp = [&](int buf, int sub, floatx16 (&out)[TP]) {
 #pragma unroll
     for (int s = 0; s < NS; ++s)
@@ -1267,8 +1269,8 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
     // previous stage: the next stage's copies go out before this stage's work
     const bool more = tile + 1 < t1;
     if (more) stage_in(tile + 1, buf ^ 1);
-    // the next group's T chains are issued ahead of this group's exp2 and
-    // products, which do not depend on them
+    // the next group's T chains (if any in this stage) are issued ahead of
+    // this group's exp2 and products, which do not depend on them
     floatx16 nxt[TP], cur[TP];
     tgrp(buf, 0, nxt);
 #pragma unroll
