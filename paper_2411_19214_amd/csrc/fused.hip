@@ -513,31 +513,44 @@ __device__ __forceinline__ void fused_pass_body(
     // the next stage's global loads go out before any of this stage's work
     if constexpr (!MAXMODE && kGrouped) __builtin_amdgcn_sched_barrier(0);
     if constexpr (MAXMODE) {
+      // the XT accumulators of MS subtiles advance together: independent
+      // MFMA chains, interleaved k-step by k-step. Two subtiles for BF16
+      // (MI355X, N = M = 1e6: 2d = 128 189 -> 182 ms, 2d = 64 99 -> 97 ms
+      // per pass), one otherwise (with FP8 rows of 2d = 256 two would spill)
+      constexpr int MS = OK == kBF16 && SUB % 2 == 0 ? 2 : 1;
 #pragma unroll
-      for (int sub = 0; sub < SUB; ++sub) {
-        const uint8_t* arow = &ys[buf][(sub * 32 + l32) * LS + h * O::SB];
-        const int asc = FP8 ? ysc[buf][sub * 32 + l32] : 127;
-        // the XT accumulators advance together: independent MFMA chains
-        floatx16 acc[XT];
+      for (int sub = 0; sub < SUB; sub += MS) {
+        const uint8_t* arow[MS];
+        int asc[MS];
+        floatx16 acc[MS][XT];
 #pragma unroll
-        for (int t = 0; t < XT; ++t) acc[t] = shv[t];
+        for (int u = 0; u < MS; ++u) {
+          arow[u] = &ys[buf][((sub + u) * 32 + l32) * LS + h * O::SB];
+          asc[u] = FP8 ? ysc[buf][(sub + u) * 32 + l32] : 127;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          const Frag f = lds_frag<OK>(arow, s);
-#pragma unroll
-          for (int t = 0; t < XT; ++t)
-            acc[t] = mfma_step<OK>(f, bfrag[t][s], acc[t], asc, xsc[t]);
+          for (int t = 0; t < XT; ++t) acc[u][t] = shv[t];
         }
 #pragma unroll
-        for (int t = 0; t < XT; ++t) {
-          float m0 = fmaxf(acc[t][0], acc[t][1]), m1 = fmaxf(acc[t][2], acc[t][3]);
+        for (int s = 0; s < NS; ++s)
 #pragma unroll
-          for (int r = 4; r < 16; r += 2) {
-            m0 = fmaxf(m0, acc[t][r]);
-            m1 = fmaxf(m1, acc[t][r + 1]);
+          for (int u = 0; u < MS; ++u) {
+            const Frag f = lds_frag<OK>(arow[u], s);
+#pragma unroll
+            for (int t = 0; t < XT; ++t)
+              acc[u][t] = mfma_step<OK>(f, bfrag[t][s], acc[u][t], asc[u], xsc[t]);
           }
-          mx[t] = fmaxf(mx[t], fmaxf(m0, m1));
-        }
+#pragma unroll
+        for (int u = 0; u < MS; ++u)
+#pragma unroll
+          for (int t = 0; t < XT; ++t) {
+            float m0 = fmaxf(acc[u][t][0], acc[u][t][1]), m1 = fmaxf(acc[u][t][2], acc[u][t][3]);
+#pragma unroll
+            for (int r = 4; r < 16; r += 2) {
+              m0 = fmaxf(m0, acc[u][t][r]);
+              m1 = fmaxf(m1, acc[u][t][r + 1]);
+            }
+            mx[t] = fmaxf(mx[t], fmaxf(m0, m1));
+          }
       }
     } else if constexpr (!kPaired && KP == 64) {
       // two accumulators at a time (the wave's two output tiles, or two
