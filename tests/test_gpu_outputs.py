@@ -115,6 +115,7 @@ def check_lists(idx, score, ref_logmu, k):
     (1000, 700, 32, "bf16", 10), (700, 1000, 32, "bf16", 16), (333, 2050, 64, "bf16", 32),
     (900, 600, 64, "fp8", 8), (50, 5, 16, "bf16", 8), (3, 1, 8, "bf16", 4),
     (700, 900, 128, "fp8", 10), (800, 500, 96, "bf16", 12), (600, 650, 128, "bf16", 32),
+    (700, 900, 64, "bf16", 10), (513, 777, 48, "bf16", 16),
     (600, 500, 64, "f32", 10), (300, 400, 128, "f32", 16), (70, 40, 16, "f32", 32)])
 def test_topk_lists_match_oracle(torch, lib, N, M, d, compute, k):
     banner(f"topk {N}x{M} d={d} {compute} k={k}")
@@ -136,17 +137,19 @@ def test_topk_lists_match_oracle(torch, lib, N, M, d, compute, k):
         check_lists(idx.cpu().numpy(), score.cpu().numpy(), ref, k)
 
 
-@pytest.mark.parametrize("compute,k,ties", [("bf16", 10, False), ("fp8", 32, False),
-                                            ("bf16", 12, True)])
-def test_topk_long_rows_match_oracle(torch, lib, compute, k, ties):
+@pytest.mark.parametrize("compute,k,ties,d", [("bf16", 10, False, 32), ("fp8", 32, False, 32),
+                                              ("bf16", 12, True, 32), ("bf16", 10, False, 64),
+                                              ("bf16", 16, True, 48)])
+def test_topk_long_rows_match_oracle(torch, lib, compute, k, ties, d):
     """256 rows over a reduced side of 70,000 rows (about 550 stages per
     workgroup, so the lists fill early and then take rare insertions), every
     row against the oracle as in the small cases; with `ties` the reduced
     rows repeat 50 distinct factor rows, so exact ties sit at the k-th
-    position."""
+    position. d = 48 and 64 with k <= 16 take the pass that interleaves two
+    subtiles' score chains."""
     import dataclasses
-    banner(f"topk 256x70000 {compute} k={k} ties={ties}")
-    N, M, d = 256, 70_000, 32
+    banner(f"topk 256x70000 d={d} {compute} k={k} ties={ties}")
+    N, M = 256, 70_000
     mk = workloads.factor_market(N, M, d, 1.0 / d, 0.5, "uint1-5", seed=7000 + k, name="seed")
     if ties:
         pool = np.random.default_rng(5).integers(0, 50, M)
