@@ -155,7 +155,12 @@ typedef struct {
   double loop_ms;        /* sweep-loop time (HIP events on `stream`)          */
   double pass_ms;        /* sum of timed reduction-pass launches (ms)         */
   int32_t pass_launches; /* number of timed reduction-pass launches           */
-  int32_t fixups;        /* rows recomputed by the exact-shift fallback       */
+  int32_t fixups;        /* rows recomputed by the exact-shift fallback (a row
+                            whose shifted sum left [2^-60, inf): two FP64
+                            passes over the reduced side inside its combine
+                            workgroup, four rows at a time, one for FP8; about
+                            2.7 ms per row at L = 2e5, d = 32 on MI355X, so a
+                            count well above zero signals a slow solve)      */
 } ipfp_result;
 
 /* ---- context ------------------------------------------------------------ */

@@ -1554,72 +1554,121 @@ __device__ __forceinline__ void block_finish(double res, int ex, double* res_slo
   }
 }
 
-// Exact fallback for a row whose shifted sum left the safe range: two passes
-// over the reduced side with FP32 dot products of the same packed operands and
-// FP64 log2 weights, the first for the maximum exponent, the second for the
-// sum; the whole workgroup works on one row. Returns log2 (K w)_o.
+// Dot product of two packed rows in FP32, one FMA chain in index order, the
+// operands read in 16-byte chunks (a row is a multiple of 64 bytes).
 template <int OK>
 __device__ __forceinline__ float dot_packed(const uint8_t* a, const uint8_t* b,
                                             int kpad) {
+  const int nc = kpad * Op<OK>::ES / 16;
   float acc = 0.f;
-  if constexpr (OK == kFP8) {
-    for (int k = 0; k < kpad; ++k) acc = fmaf(e4m3_val(a[k]), e4m3_val(b[k]), acc);
-  } else if constexpr (OK == kF32) {
-    const float* a32 = reinterpret_cast<const float*>(a);
-    const float* b32 = reinterpret_cast<const float*>(b);
-    for (int k = 0; k < kpad; ++k) acc = fmaf(a32[k], b32[k], acc);
-  } else {
-    const uint16_t* a16 = reinterpret_cast<const uint16_t*>(a);
-    const uint16_t* b16 = reinterpret_cast<const uint16_t*>(b);
-    for (int k = 0; k < kpad; ++k)
-      acc = fmaf(__uint_as_float((uint32_t)a16[k] << 16),
-                 __uint_as_float((uint32_t)b16[k] << 16), acc);
+  for (int c = 0; c < nc; ++c) {
+    const intx4 va = *reinterpret_cast<const intx4*>(a + 16 * c);
+    const intx4 vb = *reinterpret_cast<const intx4*>(b + 16 * c);
+    if constexpr (OK == kFP8) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        acc = fmaf(e4m3_val((uint8_t)((uint32_t)va[q >> 2] >> (8 * (q & 3)))),
+                   e4m3_val((uint8_t)((uint32_t)vb[q >> 2] >> (8 * (q & 3)))), acc);
+    } else if constexpr (OK == kF32) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc = fmaf(__int_as_float(va[q]), __int_as_float(vb[q]), acc);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t ua = (uint32_t)va[q >> 1], ub = (uint32_t)vb[q >> 1];
+        acc = fmaf(__uint_as_float((q & 1) ? (ua & 0xFFFF0000u) : (ua << 16)),
+                   __uint_as_float((q & 1) ? (ub & 0xFFFF0000u) : (ub << 16)), acc);
+      }
+    }
   }
   return acc;
 }
 
-template <int OK>
-__device__ __forceinline__ double exact_row_log2(const GroupHalf& p, const double* wred,
-                                                 int64_t o) {
-  __shared__ double dred[4];
+// Exact fallback for rows whose shifted sum left the safe range: two passes
+// over the reduced side with FP32 dot products of the same packed operands and
+// FP64 log2 weights, the first for the maximum exponent, the second for the
+// sum. The workgroup takes up to fix_rows(OK) rows at a time: their packed
+// rows are staged in LDS, and each reduced row's operands and weight logarithm
+// are read once for all of them (each row's own arithmetic is that of a row
+// taken alone). Writes log2 (K w)_o of rows[j] to lS[j], j < nr, in every
+// thread. Four rows (one for FP8, whose decoding takes more registers) keep
+// the combine kernels within 128 VGPRs, four workgroups per compute unit.
+constexpr int fix_rows(int ok) { return ok == kFP8 ? 1 : 4; }
+
+template <int OK, int kFixRows = fix_rows(OK)>
+__device__ __forceinline__ void exact_rows_log2(const GroupHalf& p, const double* wred,
+                                                const int64_t (&rows)[kFixRows], int nr,
+                                                double (&lS)[kFixRows]) {
+  __shared__ double dred[kFixRows][4];
+  __shared__ __attribute__((aligned(16))) uint8_t xs[kFixRows][1024];
   constexpr bool FP8 = OK == kFP8;
-  constexpr int ES = Op<OK>::ES;
-  const int kpad = p.kpad;
-  const uint8_t* xr = p.Xo + o * kpad * ES;
-  const float sx = FP8 ? p.xscale[o] : 1.f;
-  double tmax = -INFINITY;
+  const int kpad = p.kpad, rbytes = kpad * Op<OK>::ES;   // at most 1024
+  for (int j = 0; j < nr; ++j)
+    for (int c = threadIdx.x; c < rbytes / 16; c += 256)
+      reinterpret_cast<intx4*>(xs[j])[c] =
+          reinterpret_cast<const intx4*>(p.Xo + rows[j] * rbytes)[c];
+  float sx[kFixRows];
+  double tmax[kFixRows], sum[kFixRows];
+#pragma unroll
+  for (int j = 0; j < kFixRows; ++j) {
+    sx[j] = FP8 && j < nr ? p.xscale[rows[j]] : 1.f;
+    tmax[j] = -INFINITY;
+    sum[j] = 0.0;
+  }
+  __syncthreads();
   for (int64_t y = threadIdx.x; y < p.L; y += 256) {
-    const float sc = FP8 ? sx * p.yscale[y] : 1.f;
-    const double t =
-        (double)(dot_packed<OK>(xr, p.Yr + y * kpad * ES, kpad) * sc) + log2(wred[y]);
-    tmax = fmax(tmax, t);
+    const float ysc = FP8 ? p.yscale[y] : 1.f;
+    const double lw = log2(wred[y]);
+    const uint8_t* yr = p.Yr + y * rbytes;
+#pragma unroll
+    for (int j = 0; j < kFixRows; ++j)
+      if (j < nr) {
+        const float sc = FP8 ? sx[j] * ysc : 1.f;
+        tmax[j] = fmax(tmax[j], (double)(dot_packed<OK>(xs[j], yr, kpad) * sc) + lw);
+      }
   }
-  tmax = wave_max(tmax);
-  if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = tmax;
-  __syncthreads();
-  tmax = fmax(fmax(dred[0], dred[1]), fmax(dred[2], dred[3]));
-  __syncthreads();
-  double sum = 0.0;
-  if (tmax > -INFINITY) {
-    for (int64_t y = threadIdx.x; y < p.L; y += 256) {
-      const float sc = FP8 ? sx * p.yscale[y] : 1.f;
-      const double t =
-          (double)(dot_packed<OK>(xr, p.Yr + y * kpad * ES, kpad) * sc) + log2(wred[y]);
-      sum += exp2(t - tmax);
-    }
+#pragma unroll
+  for (int j = 0; j < kFixRows; ++j) {
+    if (j >= nr) break;
+    const double m = wave_max(tmax[j]);
+    if ((threadIdx.x & 63) == 0) dred[j][threadIdx.x >> 6] = m;
   }
-  sum = wave_sum(sum);
-  if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = sum;
   __syncthreads();
-  sum = (dred[0] + dred[1]) + (dred[2] + dred[3]);
+#pragma unroll
+  for (int j = 0; j < kFixRows; ++j)
+    if (j < nr) tmax[j] = fmax(fmax(dred[j][0], dred[j][1]), fmax(dred[j][2], dred[j][3]));
   __syncthreads();
-  return sum > 0.0 ? tmax + log2(sum) : -INFINITY;
+  for (int64_t y = threadIdx.x; y < p.L; y += 256) {
+    const float ysc = FP8 ? p.yscale[y] : 1.f;
+    const double lw = log2(wred[y]);
+    const uint8_t* yr = p.Yr + y * rbytes;
+#pragma unroll
+    for (int j = 0; j < kFixRows; ++j)
+      if (j < nr && tmax[j] > -INFINITY) {
+        const float sc = FP8 ? sx[j] * ysc : 1.f;
+        sum[j] += exp2((double)(dot_packed<OK>(xs[j], yr, kpad) * sc) + lw - tmax[j]);
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < kFixRows; ++j) {
+    if (j >= nr) break;
+    const double t = wave_sum(sum[j]);
+    if ((threadIdx.x & 63) == 0) dred[j][threadIdx.x >> 6] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kFixRows; ++j) {
+    if (j >= nr) break;
+    const double t = (dred[j][0] + dred[j][1]) + (dred[j][2] + dred[j][3]);
+    lS[j] = t > 0.0 ? tmax[j] + log2(t) : -INFINITY;
+  }
+  __syncthreads();
 }
 
 // Combine of one workgroup's 256 output rows: the split partial sums in fixed
 // order (FP64), the residual of the old scaling and the quadratic update of
 // eq. 6; rows whose sum left [2^-60, inf) are recomputed exactly by the whole
-// workgroup (exact_row_log2) before the block's residual and exponent maxima
+// workgroup (exact_rows_log2) before the block's residual and exponent maxima
 // are published. For the row pass (p.residual) the last workgroup to finish
 // (arrival counter in the control block) runs the convergence check, so a
 // sweep needs no separate fallback or check launch.
@@ -1657,14 +1706,20 @@ __device__ __forceinline__ void combine_body(const GroupHalf& p, const int bid,
   const int nb = nbad;
   if (nb > 0) {
     const double* wred = p.red_dbuf ? p.wred + (int64_t)(i & 1) * p.L : p.wred;
-    for (int k = 0; k < nb; ++k) {
-      const int t = bad[k];
-      const int64_t ob = (int64_t)bid * 256 + t;
-      const double lS = exact_row_log2<OK>(p, wred, ob);
-      if (threadIdx.x == t) {
-        res = finish_row(ob, lS, p.marg, w_old, w_new, p.residual != 0, ctl);
-        ex = exponent_of(w_new[ob]);
-      }
+    constexpr int kFixRows = fix_rows(OK);
+    for (int k0 = 0; k0 < nb; k0 += kFixRows) {
+      const int nr = min(kFixRows, nb - k0);
+      int64_t rows[kFixRows];
+      double lS[kFixRows];
+#pragma unroll
+      for (int j = 0; j < kFixRows; ++j) rows[j] = (int64_t)bid * 256 + bad[k0 + min(j, nr - 1)];
+      exact_rows_log2<OK>(p, wred, rows, nr, lS);
+#pragma unroll
+      for (int j = 0; j < kFixRows; ++j)
+        if (j < nr && (int)threadIdx.x == bad[k0 + j]) {
+          res = finish_row(rows[j], lS[j], p.marg, w_old, w_new, p.residual != 0, ctl);
+          ex = exponent_of(w_new[rows[j]]);
+        }
     }
     if (threadIdx.x == 0) atomicAdd(&ctl->fix_total, nb);
   }
