@@ -875,13 +875,28 @@ __global__ void __launch_bounds__(256)
   // T of TP subtiles (MFMA chains over the packed rows), interleaved k-step
   // by k-step so that consecutive MFMAs are independent
   constexpr int TP = topk_tp<KP, OK, KT>();
+  // BF16 and FP32 chains start from the reduced rows' log2 weights, so the
+  // score comes out of the MFMAs (their FP32 sums keep it well inside the
+  // lists' tolerance); the FP8 MFMA adds its inputs at reduced precision, so
+  // there the weights are added after the chain
+  constexpr bool kLwIn = OK != kFP8;
   auto tgrp = [&](int buf, int sub, floatx16 (&out)[TP]) {
     int asc[TP];
 #pragma unroll
     for (int u = 0; u < TP; ++u) {
       asc[u] = FP8 ? ysc[buf][(sub + u) * 32 + l32] : 127;
+      if constexpr (kLwIn) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) out[u][r] = 0.f;
+        for (int g = 0; g < 4; ++g) {
+          const floatx4 w4 =
+              *reinterpret_cast<const floatx4*>(&lws[buf][(sub + u) * 32 + 8 * g + 4 * h]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) out[u][4 * g + e] = w4[e];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) out[u][r] = 0.f;
+      }
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s)
@@ -912,7 +927,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int yr = sub * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        sc[r] = acc[r] + lws[buf][yr];
+        sc[r] = kLwIn ? acc[r] : acc[r] + lws[buf][yr];
         top = fmaxf(top, sc[r]);
       }
       if (top > ts[KT - 1]) {
