@@ -778,10 +778,10 @@ __device__ __forceinline__ void topk_insert(float (&ts)[KT], int (&ti)[KT], floa
 // Subtiles whose score chains a top-k pass interleaves (consecutive MFMAs
 // then never wait on each other): two for BF16 rows of 2d = 96 and 128 with
 // lists of up to 16, which still fit the two waves per SIMD that one chain
-// ran at; else one. MI355X, N = M = 1e6, k = 10, one chain -> two: BF16
-// 2d = 128 332 -> 327 ms, 2d = 96 282 -> 278 ms, 2d = 64 unchanged; FP8
-// 2d = 128 and 192 3 % slower (their MFMA is half as long, and the check
-// work dominates).
+// ran at; else one. MI355X, N = M = 1e6, k = 10, one chain -> two (with the
+// weights in the chains): BF16 2d = 128 319 -> 300 ms, 2d = 96 271 -> 256
+// ms, 2d = 64 187 -> 214 ms; FP8 2d = 128 and 192 3 % slower (their MFMA
+// is half as long, and the check work dominates).
 template <int KP, int OK, int KT>
 constexpr int topk_tp() {
   return PassCore<KP, 1, 4, OK>::SUB >= 4 && OK == kBF16 && KP >= 96 && KT <= 16 ? 2 : 1;
@@ -1277,9 +1277,10 @@ __global__ void __launch_bounds__(kGradWaves * 64) __attribute__((amdgpu_waves_p
 #pragma unroll
   for (int j = 0; j < 16; ++j) shv[j] = hv;
   // TP subtiles' chains at a time, interleaved k-step by k-step, so that
-  // consecutive MFMAs are independent: all four of a stage when it has four
-  // (MI355X, C3: 912 ms with one chain at a time, 874 with two, 849 with
-  // four, the same sums bit for bit), else one
+  // consecutive MFMAs are independent: all four of a stage when it has four,
+  // else one (MI355X, C3, each against the build before it on one box: one
+  // chain -> two, with the products paired, 912 -> 874 ms; two -> four 860
+  // -> 849 ms; the same sums bit for bit)
   constexpr int TP = SUB >= 4 ? 4 : 1;
   auto tgrp = [&](int buf, int sub, floatx16 (&out)[TP]) {
 #pragma unroll
