@@ -310,7 +310,9 @@ int ipfp_stable_factors(ipfp_ctx *ctx, const ipfp_market *mk, const double *a,
  * side 1 every employer y the k candidates x with the largest mu_xy (the
  * reciprocal recommendation of Sec. 4.1, ranked by the stable matching).
  * Scores are formed from the packed operands the solve uses: log mu_xy =
- * ln 2 (T_xy + log2 a_x + log2 b_y), T from the matrix cores in FP32. idx_out
+ * ln 2 (T_xy + log2 a_x + log2 b_y), T from the matrix cores in FP32 (for
+ * BF16 and FP32 operands the reduced side's log2 weight is the MFMA chain's
+ * initial accumulator; for FP8 it is added after the chain). idx_out
  * (rows x k int32, device) lists indices best first, score_out (rows x k
  * float, device) the matching log mu; entries beyond the other side's size
  * are -1 / -inf. Equal scores keep the lower index of a lane's stream, so the
